@@ -1,0 +1,209 @@
+/*
+ * hdc.h -- C ABI of the MI355X (gfx950) generic map / reduce library.
+ *
+ * The operation: one generic callable applied element by element over a
+ * device array (map), and the results folded into a sum (transform_reduce,
+ * dot, segmented reduce).  The paper's kernels take a callable *by value* and
+ * invoke it in every device thread (section 2.4, listing
+ * lst_solution_ifdef_cudaarch; section 2.6, listing
+ * lst_solution_exp_constexpr_la); which overload runs is decided at compile
+ * time from the callable's type through the Host-Device-Compatibility tag
+ * (section 2.7, listing lst_hst_dev_tags; section 2.10 "SFINAE 3 with macro";
+ * appendix B, listing lst_hdc).  A C ABI cannot carry templates, so the
+ * callable crosses this boundary as a closed set of functor ids plus their
+ * parameters (hdc_functor); inside the library every id is a concrete C++
+ * type tagged HstDev whose call is fully inlined into its kernel -- there is
+ * no per-element indirect call.
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers named x, y, z, out, offsets, workspace are DEVICE pointers owned
+ *    by the caller; the library never frees them and keeps no reference after
+ *    the call returns (a captured graph references them for its lifetime).
+ *  - `stream` is a hipStream_t passed as void*; NULL means the legacy default
+ *    stream.  Work is stream-ordered and asynchronous: results are valid after
+ *    the caller synchronises the stream.
+ *  - Element pointers must be aligned to their element size; any further
+ *    alignment is handled inside (unaligned heads and tails are peeled).
+ *  - Every argument check runs on the host BEFORE anything is enqueued, so a
+ *    call that returns an error has written nothing.  Errors are reported by
+ *    the return code (HDC_OK == 0 is success, as the paper's error-code
+ *    convention in section 1.2, "Cuda error checking"); a thread-local text
+ *    explaining the last failure is available from hdc_last_error().
+ *  - Device faults are sticky and surface at the caller's next
+ *    synchronisation (section 2.4, variant "no sensible implementation").
+ *  - Calls from several host threads are safe.  Calls that share one
+ *    workspace buffer must be ordered on one stream.
+ */
+#ifndef HDC_H
+#define HDC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hdc_status {
+  HDC_OK = 0,
+  HDC_ERR_INVALID_ARGUMENT = 1, /* null pointer, negative size, bad alignment */
+  HDC_ERR_UNSUPPORTED = 2,      /* functor / dtype / accumulation not provided */
+  HDC_ERR_WORKSPACE = 3,        /* workspace too small, or growth while capturing */
+  HDC_ERR_HIP = 4               /* a HIP runtime call or kernel launch failed */
+} hdc_status;
+
+typedef enum hdc_dtype {
+  HDC_F32 = 0,  /* IEEE binary32 */
+  HDC_F16 = 1,  /* IEEE binary16 */
+  HDC_BF16 = 2, /* bfloat16 (upper half of binary32) */
+  HDC_I32 = 3,  /* two's-complement int32 */
+  HDC_I64 = 4,  /* declared for completeness; no operation accepts it yet */
+  HDC_F64 = 5   /* declared for completeness; no operation accepts it yet */
+} hdc_dtype;
+
+typedef enum hdc_fn {
+  HDC_FN_IDENTITY = 0, /* f(x) = x */
+  HDC_FN_AFFINE = 1,   /* floats: f(x) = fma(a, x, b) in fp32 (one rounding);
+                          int32: f(x) = ia*x + ib with two's-complement wrap
+                          (map: mod 2^32; reduce terms: mod 2^64) */
+  HDC_FN_HORNER = 2,   /* f(x) = sum_{k<=degree} coef[k] x^k, evaluated as
+                          acc = coef[degree]; acc = fma(acc, x, coef[k]),
+                          k = degree-1 .. 0, in fp32 (floats only) */
+  HDC_FN_PRODUCT = 3   /* dot-product term x[i]*z[i]; transform_reduce only */
+} hdc_fn;
+
+typedef enum hdc_accum {
+  HDC_ACC_PLAIN = 0,       /* floats: fp32 partial sums; `out` is one float */
+  HDC_ACC_COMPENSATED = 1, /* floats: fp32 TwoSum-compensated partials, fp64
+                              final cross-block combine; `out` is one double */
+  HDC_ACC_EXACT_INT = 2    /* int32: int64 sums wrapping mod 2^64; `out` is
+                              one int64 */
+} hdc_accum;
+
+typedef enum hdc_op {
+  HDC_OP_MAP = 0,
+  HDC_OP_TRANSFORM_REDUCE = 1,
+  HDC_OP_SEGMENTED_REDUCE = 2,
+  HDC_OP_MAP_REDUCE = 3
+} hdc_op;
+
+#define HDC_MAX_DEGREE 16
+
+/* The callable.  Fields not used by `id` are ignored. */
+typedef struct hdc_functor {
+  int32_t id;                    /* hdc_fn */
+  int32_t degree;                /* HORNER: 0 .. HDC_MAX_DEGREE */
+  float a, b;                    /* AFFINE on floating-point storage */
+  float coef[HDC_MAX_DEGREE + 1]; /* HORNER: coef[k] multiplies x^k */
+  int64_t ia, ib;                /* AFFINE on int32 storage */
+} hdc_functor;
+
+/*
+ * y[i] = f(x[i]) for 0 <= i < n, written in x's storage type.
+ *   Floats: f evaluated in fp32 on the exactly widened input; fp16 / bf16
+ *   results are rounded to nearest-even.  IDENTITY copies bits.
+ *   Supported: IDENTITY, AFFINE on F32/F16/BF16/I32; HORNER on F32/F16/BF16.
+ *   x == y (in place) is allowed; partial overlap is rejected.  n == 0 is a
+ *   no-op.  Bytes moved: 2 n sizeof(element).
+ */
+hdc_status hdc_map(const hdc_functor* f, hdc_dtype dt, const void* x, void* y,
+                   int64_t n, void* stream);
+
+/*
+ * out = sum_i f(x[i])  (PRODUCT: sum_i x[i] * z[i], z of the same dtype).
+ *   acc PLAIN or COMPENSATED for F32/F16/BF16, EXACT_INT for I32 (IDENTITY
+ *   or AFFINE).  n == 0 writes 0.  The summation order is fixed by (n, the
+ *   tuning in force): results are bit-reproducible run to run, but a
+ *   different tuning may change the last bits of a floating-point result.
+ *   workspace: device scratch of at least hdc_workspace_size(...) bytes, or
+ *   NULL to use a library-owned buffer (per device and stream, grown outside
+ *   graph capture only).  Bytes moved: n sizeof(element) (x2 for PRODUCT).
+ */
+hdc_status hdc_transform_reduce(const hdc_functor* f, hdc_dtype dt,
+                                const void* x, const void* z, int64_t n,
+                                hdc_accum acc, void* out, void* workspace,
+                                size_t ws_bytes, void* stream);
+
+/*
+ * out[j] = sum_{offsets[j] <= i < offsets[j+1]} f(x[i]) for 0 <= j < S.
+ *   offsets: device int64 array of S+1 entries, non-decreasing, offsets[0] >= 0
+ *   (a precondition, not checked per call: checking it would need a device
+ *   round trip; hdc_validate_offsets checks it synchronously).
+ *   out: S floats (PLAIN), doubles (COMPENSATED) or int64 (EXACT_INT).
+ *   Empty segments give 0.  The whole batch is one plan pass, one
+ *   persistent pass and one combine pass, with no host synchronisation.
+ *   IDENTITY, AFFINE, HORNER as for transform_reduce (no PRODUCT).
+ *   `total` is an upper bound on offsets[S] (used to size the work list).
+ */
+hdc_status hdc_segmented_reduce(const hdc_functor* f, hdc_dtype dt,
+                                const void* x, const int64_t* offsets,
+                                int64_t num_segments, int64_t total,
+                                hdc_accum acc, void* out, void* workspace,
+                                size_t ws_bytes, void* stream);
+
+/*
+ * Fused map + transform_reduce: y[i] = f(x[i]) as hdc_map, and
+ * out = the fold of g over x as hdc_transform_reduce(g, ...), reading x once.
+ *   Bytes moved: 2 n sizeof(element) instead of 3.
+ */
+hdc_status hdc_map_reduce(const hdc_functor* f, const hdc_functor* g,
+                          hdc_dtype dt, const void* x, void* y, int64_t n,
+                          hdc_accum acc, void* out, void* workspace,
+                          size_t ws_bytes, void* stream);
+
+/* Bytes of workspace `op` needs for these sizes (0 for HDC_OP_MAP). */
+hdc_status hdc_workspace_size(int op, hdc_dtype dt, hdc_accum acc, int64_t n,
+                              int64_t num_segments, size_t* bytes);
+
+/* Synchronous check of a CSR offsets array (device pointer): returns HDC_OK
+ * when it is non-decreasing with offsets[0] >= 0 and offsets[S] <= total.
+ * For tests and debugging; it copies the array to the host. */
+hdc_status hdc_validate_offsets(const int64_t* offsets, int64_t num_segments,
+                                int64_t total, void* stream);
+
+/* Tuning of one class of calls: (op, dtype, accumulation, size bucket).
+ * Buckets split n (the element count; for the segmented op, the total) at
+ * 2^16, 2^20 and 2^24 into buckets 0..3.  block: threads per block (64..1024,
+ * multiple of 64); unroll: 16-byte vectors per lane per step (1, 2, 4 or 8);
+ * grid_mult: blocks per compute unit (1..64); chunk: elements per work item
+ * of the segmented pass (power of two, 1024..65536); small_seg: segments at
+ * most this long are packed several per wavefront (0..1024); seg_per_wave:
+ * how many small segments share one wavefront (power of two, 1..64, each
+ * served by 64/seg_per_wave lanes).  Tuning changes
+ * the summation order, so the last bits of a floating-point sum may change;
+ * results stay within the stated tolerance. */
+typedef struct hdc_tuning {
+  int32_t block;
+  int32_t unroll;
+  int32_t grid_mult;
+  int32_t chunk;
+  int32_t small_seg;
+  int32_t seg_per_wave;
+} hdc_tuning;
+
+/* Set the class (bucket -1: every bucket); fields set to 0 keep their value.
+ * Nothing changes if any resulting value is out of range. */
+hdc_status hdc_set_tuning(int op, hdc_dtype dt, hdc_accum acc, int bucket,
+                          const hdc_tuning* t);
+hdc_status hdc_get_tuning(int op, hdc_dtype dt, hdc_accum acc, int bucket,
+                          hdc_tuning* t);
+/* The size bucket a call of n elements falls in. */
+hdc_status hdc_tuning_bucket(int64_t n, int32_t* bucket);
+/* Load a tuning cache written by the autotuner: one line per class,
+ * "op dtype acc bucket block unroll grid_mult chunk small_seg seg_per_wave",
+ * '#' starts a
+ * comment line.  NULL reads the path in the HDC_TUNE_CACHE environment
+ * variable (which is also read once, before the first call).  A missing file
+ * is not an error; a malformed line is reported and skipped. */
+hdc_status hdc_load_tuning(const char* path);
+
+const char* hdc_status_string(hdc_status s);
+/* Thread-local explanation of the last non-OK status on this thread. */
+const char* hdc_last_error(void);
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t hdc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HDC_H */

@@ -1,0 +1,317 @@
+// Kernels of the map / reduce path.  Every kernel takes its callable by value
+// and calls it once per element (section 2.4, listing
+// lst_solution_ifdef_cudaarch: a kernel template over the callable type);
+// each is constrained to device-capable callables (section 2.7, "SFINAE 1*",
+// in its C++20 `requires` form), so a host-only callable fails to compile.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "hdc_device.hpp"
+#include "hdc_functors.hpp"
+
+namespace hdc {
+
+// How an array of n elements is walked.  Vector mode: `head` leading
+// elements up to the first 16-byte boundary, `nvec` aligned 16-byte vectors,
+// then `tail` trailing elements starting at `tail_start`.  Scalar mode (used
+// when two operands disagree in alignment): all n elements one by one.
+struct Range {
+  int64_t n;
+  int64_t head;
+  int64_t nvec;
+  int64_t tail_start;
+  int64_t tail;
+};
+
+template <class S>
+using elem_t = typename S::T;
+
+// ---------------------------------------------------------------------------
+// Element operations
+// ---------------------------------------------------------------------------
+
+template <class F, class S>
+__device__ __forceinline__ elem_t<S> map_elem(const F& f, elem_t<S> x) {
+  if constexpr (std::is_same_v<S, I32>)
+    return f.map(x);
+  else if constexpr (std::is_same_v<F, Identity>)
+    return x;  // bit copy, NaN payloads included
+  else
+    return S::narrow(f(S::widen(x)));
+}
+
+template <class F, class S, class Acc>
+__device__ __forceinline__ void fold_elem(Acc& a, const F& f, elem_t<S> x, elem_t<S> z) {
+  if constexpr (std::is_same_v<S, I32>) {
+    a.add(f.term(x));
+  } else if constexpr (F::binary) {
+    if constexpr (std::is_same_v<Acc, CompAcc>)
+      a.template add_product<!std::is_same_v<S, F32>>(S::widen(x), S::widen(z));  // 16-bit products are exact in fp32
+    else
+      a.add_product(S::widen(x), S::widen(z));
+  } else {
+    a.add(f(S::widen(x)));
+  }
+}
+
+// Evaluate a floating-point callable on a batch of widened values in place.
+// Horner runs coefficient-outermost so that each coefficient (a uniform
+// value) feeds N independent fma chains; each element still sees exactly the
+// fma sequence of Horner::operator(), so results are bit-identical to it.
+template <class F, int N>
+__device__ __forceinline__ void eval_batch(const F& f, float (&t)[N]) {
+  if constexpr (std::is_same_v<F, Horner>) {
+    float acc[N];
+    const float top = f.c[f.degree];
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc[i] = top;
+    for (int k = f.degree - 1; k >= 0; --k) {
+      const float ck = f.c[k];
+#pragma unroll
+      for (int i = 0; i < N; ++i) acc[i] = __builtin_fmaf(acc[i], t[i], ck);
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) t[i] = acc[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) t[i] = f(t[i]);
+  }
+}
+
+// Map a batch of storage values: widen, evaluate, narrow (bit copy for
+// Identity, integer map for int32 storage).
+template <class F, class S, int N>
+__device__ __forceinline__ void map_batch(const F& f, const elem_t<S> (&in)[N], elem_t<S> (&out)[N]) {
+  if constexpr (std::is_same_v<S, I32> || std::is_same_v<F, Identity>) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i] = map_elem<F, S>(f, in[i]);
+  } else {
+    float t[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) t[i] = S::widen(in[i]);
+    eval_batch(f, t);
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i] = S::narrow(t[i]);
+  }
+}
+
+template <class Acc>
+struct MergeOp {
+  __device__ Acc operator()(Acc a, Acc b) const { return Acc::merge(a, b); }
+};
+
+// ---------------------------------------------------------------------------
+// map: y[i] = f(x[i])
+// ---------------------------------------------------------------------------
+
+template <class F, class S, int U, bool kVector>
+  requires device_callable<F>
+__global__ __launch_bounds__(1024) void map_kernel(F f, const elem_t<S>* x, elem_t<S>* y, Range r) {
+  const int64_t B = blockDim.x;
+  const int64_t tid = threadIdx.x;
+  if constexpr (kVector) {
+    const elem_t<S>* xv = x + r.head;
+    elem_t<S>* yv = y + r.head;
+    const int64_t nchunk = (r.nvec + B * U - 1) / (B * U);
+    for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
+      const int64_t base = c * B * U + tid;
+      const bool full = c * B * U + B * U <= r.nvec;
+      elem_t<S> in[U * S::kVec], out[U * S::kVec];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        Vec<S> v{};
+        if (full || base + u * B < r.nvec) v = load16<S>(xv + (base + u * B) * S::kVec);
+#pragma unroll
+        for (int k = 0; k < S::kVec; ++k) in[u * S::kVec + k] = v.e[k];
+      }
+      map_batch<F, S>(f, in, out);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (full || base + u * B < r.nvec) {
+          Vec<S> o;
+#pragma unroll
+          for (int k = 0; k < S::kVec; ++k) o.e[k] = out[u * S::kVec + k];
+          store16_nt<S>(yv + (base + u * B) * S::kVec, o);
+        }
+      }
+    }
+    // Unaligned head and tail: the last block's first threads.
+    if (blockIdx.x == gridDim.x - 1) {
+      if (tid < r.head) y[tid] = map_elem<F, S>(f, x[tid]);
+      if (tid < r.tail) y[r.tail_start + tid] = map_elem<F, S>(f, x[r.tail_start + tid]);
+    }
+  } else {
+    const int64_t stride = (int64_t)gridDim.x * B;
+    for (int64_t i = blockIdx.x * B + tid; i < r.n; i += stride * U) {
+      elem_t<S> v[U], o[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = (i + u * stride < r.n) ? x[i + u * stride] : elem_t<S>{};
+      map_batch<F, S>(f, v, o);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (i + u * stride < r.n) y[i + u * stride] = o[u];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// transform_reduce pass 1: every block folds its share into one partial.
+// Each lane keeps kVec independent fold states (one per vector component);
+// they are merged in component order, then across the wavefront (DPP), then
+// across wavefronts (LDS) in wave order.  The block-to-data mapping depends
+// only on (n, block, unroll, grid), so the partials are reproducible.
+// With kMap, the same pass also writes y[i] = fm(x[i]) (fused map + reduce).
+// ---------------------------------------------------------------------------
+
+template <class F, class S, class Acc, int U, bool kVector, class FM = Identity, bool kMap = false>
+  requires device_callable<F> && device_callable<FM>
+__global__ __launch_bounds__(1024) void reduce_kernel(F f, const elem_t<S>* x, const elem_t<S>* z, Range r,
+                                                      Acc* partials, FM fm = FM{}, elem_t<S>* y = nullptr) {
+  __shared__ Acc lds[kMaxWaves];
+  const int64_t B = blockDim.x;
+  const int64_t tid = threadIdx.x;
+  constexpr bool kInt = std::is_same_v<S, I32>;
+  constexpr bool kBatch = !kInt && !F::binary;  // unary float callables run as one batch
+  constexpr int K = kVector ? S::kVec : U;
+  constexpr int N = kVector ? U * S::kVec : U;  // elements per lane per step
+  Acc acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = Acc::zero();
+
+  // Fold N loaded elements; `ok(i)` tells whether element slot i is real.
+  auto fold_step = [&](const elem_t<S>(&v)[N], const elem_t<S>(&w)[N], auto ok) {
+    if constexpr (kBatch) {
+      float t[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) t[i] = S::widen(v[i]);
+      eval_batch(f, t);
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+        if (ok(i)) acc[i % K].add(t[i]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+        if (ok(i)) fold_elem<F, S>(acc[i % K], f, v[i], w[i]);
+    }
+  };
+
+  if constexpr (kVector) {
+    const elem_t<S>* xv = x + r.head;
+    const elem_t<S>* zv = F::binary ? z + r.head : nullptr;
+    const int64_t nchunk = (r.nvec + B * U - 1) / (B * U);
+    for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
+      const int64_t base = c * B * U + tid;
+      const bool full = c * B * U + B * U <= r.nvec;
+      elem_t<S> v[N], w[N];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        Vec<S> a{}, b{};
+        if (full || base + u * B < r.nvec) {
+          a = load16<S>(xv + (base + u * B) * S::kVec);
+          if constexpr (F::binary) b = load16<S>(zv + (base + u * B) * S::kVec);
+        }
+#pragma unroll
+        for (int k = 0; k < S::kVec; ++k) {
+          v[u * S::kVec + k] = a.e[k];
+          w[u * S::kVec + k] = b.e[k];
+        }
+      }
+      fold_step(v, w, [&](int i) { return full || base + (i / S::kVec) * B < r.nvec; });
+      if constexpr (kMap) {
+        elem_t<S> o[N];
+        map_batch<FM, S>(fm, v, o);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (full || base + u * B < r.nvec) {
+            Vec<S> ov;
+#pragma unroll
+            for (int k = 0; k < S::kVec; ++k) ov.e[k] = o[u * S::kVec + k];
+            store16_nt<S>(y + r.head + (base + u * B) * S::kVec, ov);
+          }
+        }
+      }
+    }
+    if (blockIdx.x == gridDim.x - 1) {
+      if (tid < r.head) {
+        fold_elem<F, S>(acc[0], f, x[tid], F::binary ? z[tid] : x[tid]);
+        if constexpr (kMap) y[tid] = map_elem<FM, S>(fm, x[tid]);
+      }
+      if (tid < r.tail) {
+        const int64_t i = r.tail_start + tid;
+        fold_elem<F, S>(acc[1 % K], f, x[i], F::binary ? z[i] : x[i]);
+        if constexpr (kMap) y[i] = map_elem<FM, S>(fm, x[i]);
+      }
+    }
+  } else {
+    const int64_t stride = (int64_t)gridDim.x * B;
+    for (int64_t i = blockIdx.x * B + tid; i < r.n; i += stride * U) {
+      elem_t<S> v[N], w[N];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool ok = i + u * stride < r.n;
+        v[u] = ok ? x[i + u * stride] : elem_t<S>{};
+        if constexpr (F::binary) w[u] = ok ? z[i + u * stride] : elem_t<S>{};
+        else w[u] = v[u];
+      }
+      fold_step(v, w, [&](int u) { return i + u * stride < r.n; });
+      if constexpr (kMap) {
+        elem_t<S> o[N];
+        map_batch<FM, S>(fm, v, o);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (i + u * stride < r.n) y[i + u * stride] = o[u];
+      }
+    }
+  }
+
+  Acc t = acc[0];
+#pragma unroll
+  for (int k = 1; k < K; ++k) t = Acc::merge(t, acc[k]);
+  t = block_reduce(t, MergeOp<Acc>{}, lds);
+  if (tid == 0) partials[blockIdx.x] = t;
+}
+
+// ---------------------------------------------------------------------------
+// transform_reduce pass 2: one block folds the G partials in index order
+// (thread-strided, then the fixed block reduction) and writes the result.
+//   PlainAcc -> float (fp32 sum); CompAcc -> double (fp64 sum of s + c, or of
+//   s alone when s is not finite: TwoSum of an infinity yields NaN in c);
+//   IntAcc -> int64 (wrapping).
+// ---------------------------------------------------------------------------
+
+struct AddF32 { __device__ float operator()(float a, float b) const { return a + b; } };
+struct AddF64 { __device__ double operator()(double a, double b) const { return a + b; } };
+struct AddU64 { __device__ uint64_t operator()(uint64_t a, uint64_t b) const { return a + b; } };
+
+template <class Acc>
+__global__ __launch_bounds__(256) void reduce_final_kernel(const Acc* partials, int G, void* out) {
+  const int tid = threadIdx.x;
+  if constexpr (std::is_same_v<Acc, PlainAcc>) {
+    __shared__ float lds[kMaxWaves];
+    float s = 0.0f;
+    for (int i = tid; i < G; i += blockDim.x) s += partials[i].s;
+    s = block_reduce(s, AddF32{}, lds);
+    if (tid == 0) *static_cast<float*>(out) = s;
+  } else if constexpr (std::is_same_v<Acc, CompAcc>) {
+    __shared__ double lds[kMaxWaves];
+    double s = 0.0;
+    for (int i = tid; i < G; i += blockDim.x) {
+      const CompAcc p = partials[i];
+      s += __builtin_isfinite(p.s) ? (double)p.s + (double)p.c : (double)p.s;
+    }
+    s = block_reduce(s, AddF64{}, lds);
+    if (tid == 0) *static_cast<double*>(out) = s;
+  } else {
+    __shared__ uint64_t lds[kMaxWaves];
+    uint64_t s = 0;
+    for (int i = tid; i < G; i += blockDim.x) s += partials[i].s;
+    s = block_reduce(s, AddU64{}, lds);
+    if (tid == 0) *static_cast<int64_t*>(out) = (int64_t)s;
+  }
+}
+
+}  // namespace hdc

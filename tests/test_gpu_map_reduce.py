@@ -1,0 +1,262 @@
+"""GPU parity of hdc_map / hdc_transform_reduce / hdc_map_reduce against the
+CPU oracle, through the C ABI (the Python binding only marshals arguments).
+
+Bars: map outputs and integer sums bit-exact; floating-point sums within
+1e-6 * sum|terms| of the exact sum (and exactly 0 when every term is 0).
+"""
+import itertools
+import math
+
+import pytest
+import torch
+
+import oracle
+import paper_2309_03912_amd as hdc
+import synth
+
+pytestmark = pytest.mark.gpu
+
+COEF8 = synth.horner_coefficients(8)
+FNS = {
+    "identity": {"fn": "identity"},
+    "affine": {"fn": "affine", "a": 2.5, "b": 0.5},
+    "horner": {"fn": "horner", "coef": COEF8},
+}
+INT_FNS = {"identity": {"fn": "identity"}, "affine": {"fn": "affine", "a": 3, "b": -7}}
+FLOAT_DTYPES = [torch.float32, torch.float16, torch.bfloat16]
+SIZES = [0, 1, 3, 7, 8, 9, 63, 64, 65, 255, 1000, 4097, 65541, (1 << 20) + 3]
+TOL = 1e-6
+
+
+def gpu():
+    return torch.device("cuda", 0)
+
+
+def make_x(n, dt, seed=1, stream=0, scale=1.0):
+    if dt == torch.int32:
+        return synth.uniform_int(seed, stream, n, bits=20)
+    return synth.to_storage(synth.uniform_pm1_f32(seed, stream, n).double() * scale, dt)
+
+
+def bits(t):
+    return t.view(torch.int16) if t.element_size() == 2 else t.view(torch.int32)
+
+
+def assert_close_sum(got, ref, what=""):
+    exact, A = ref["exact"], ref["abs_sum"]
+    if A == 0:
+        assert got == 0.0, what
+        return
+    assert abs(got - exact) <= TOL * A, f"{what}: got {got!r} exact {exact!r} A {A!r}"
+
+
+# --------------------------------------------------------------------------
+# map
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dt", FLOAT_DTYPES)
+@pytest.mark.parametrize("name", list(FNS))
+def test_map_float_bit_exact(dt, name):
+    for n in SIZES:
+        x = make_x(n, dt, seed=n + 1, scale=3.0)
+        y = hdc.map(x.to(gpu()), FNS[name])
+        ref = oracle.map(FNS[name], x)
+        assert torch.equal(bits(y.cpu()), bits(ref)), (name, dt, n)
+
+
+@pytest.mark.parametrize("name", list(INT_FNS))
+def test_map_int_bit_exact(name):
+    for n in SIZES:
+        x = make_x(n, torch.int32, seed=n + 2)
+        y = hdc.map(x.to(gpu()), INT_FNS[name])
+        assert torch.equal(y.cpu(), oracle.map(INT_FNS[name], x)), (name, n)
+    x = torch.tensor([0, 1, -1, 2 ** 31 - 1, -2 ** 31, 123456789], dtype=torch.int32)
+    assert torch.equal(hdc.map(x.to(gpu()), INT_FNS["affine"]).cpu(), oracle.map(INT_FNS["affine"], x))
+
+
+@pytest.mark.parametrize("dt", FLOAT_DTYPES + [torch.int32])
+def test_map_misaligned_views_and_in_place(dt):
+    n = 100003
+    fn = FNS["affine"] if dt != torch.int32 else INT_FNS["affine"]
+    base = make_x(n + 16, dt, seed=5)
+    ref_all = oracle.map(fn, base)
+    g = base.to(gpu())
+    for xo, yo in [(1, 1), (1, 3), (3, 0), (0, 5), (7, 7)]:
+        out = torch.zeros(n + 16, dtype=dt, device=gpu())
+        hdc.map(g[xo:xo + n], fn, out=out[yo:yo + n])
+        assert torch.equal(bits(out[yo:yo + n].cpu()), bits(ref_all[xo:xo + n])), (xo, yo)
+        assert torch.equal(bits(out[:yo].cpu()), bits(torch.zeros(yo, dtype=dt)))  # nothing written outside
+        assert torch.equal(bits(out[yo + n:].cpu()), bits(torch.zeros(16 - yo, dtype=dt)))
+    h = g.clone()
+    hdc.map(h[2:2 + n], fn, out=h[2:2 + n])
+    assert torch.equal(bits(h[2:2 + n].cpu()), bits(ref_all[2:2 + n]))
+
+
+def test_map_special_values_f32():
+    x = torch.tensor([0.0, -0.0, math.inf, -math.inf, 1e-45, -1e-45, 3.4e38, -3.4e38, 1.17549435e-38],
+                     dtype=torch.float32)
+    for name, fn in FNS.items():
+        y = hdc.map(x.to(gpu()), fn).cpu()
+        ref = oracle.map(fn, x)
+        assert torch.equal(torch.isnan(y), torch.isnan(ref)), name
+        m = ~torch.isnan(ref)
+        assert torch.equal(bits(y[m]), bits(ref[m])), name
+
+
+@pytest.mark.parametrize("dt", [torch.float16, torch.bfloat16])
+def test_map_16bit_rounding_all_patterns(dt):
+    # every finite 16-bit value through f(x) = 2.5 x + 0.5: exercises RNE, overflow and subnormals
+    x = torch.arange(-32768, 32768, dtype=torch.int32).to(torch.int16).view(dt)
+    x = x[torch.isfinite(x.float())]
+    y = hdc.map(x.to(gpu()), FNS["affine"]).cpu()
+    ref = oracle.map(FNS["affine"], x)
+    assert torch.equal(torch.isnan(y.float()), torch.isnan(ref.float()))
+    m = ~torch.isnan(ref.float())
+    assert torch.equal(bits(y[m]), bits(ref[m]))
+
+
+# --------------------------------------------------------------------------
+# transform_reduce
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("acc", ["plain", "compensated"])
+@pytest.mark.parametrize("dt", FLOAT_DTYPES)
+@pytest.mark.parametrize("name", list(FNS))
+def test_transform_reduce_float(acc, dt, name):
+    for n in SIZES:
+        x = make_x(n, dt, seed=n + 3)
+        r = hdc.transform_reduce(x.to(gpu()), FNS[name], acc).item()
+        assert_close_sum(r, oracle.reduce(FNS[name], x), f"{name} {dt} {acc} n={n}")
+
+
+@pytest.mark.parametrize("acc", ["plain", "compensated"])
+@pytest.mark.parametrize("dt", FLOAT_DTYPES)
+def test_dot(acc, dt):
+    for n in SIZES:
+        x = synth.to_storage(synth.normal_f64(n + 4, 9, n), dt)
+        z = synth.to_storage(synth.normal_f64(n + 4, 1, n), dt)
+        r = hdc.transform_reduce(x.to(gpu()), {"fn": "product"}, acc, z=z.to(gpu())).item()
+        assert_close_sum(r, oracle.reduce({"fn": "product"}, x, z), f"dot {dt} {acc} n={n}")
+
+
+def test_dot_closed_form_and_misaligned_operands():
+    n = 100003
+    x = torch.ones(n + 8)
+    z = (torch.arange(n + 8) % 16).float()
+    g, h = x.to(gpu()), z.to(gpu())
+    for xo, zo in [(0, 0), (1, 1), (1, 2), (3, 0)]:
+        r = hdc.transform_reduce(g[xo:xo + n], {"fn": "product"}, "plain", z=h[zo:zo + n]).item()
+        ref = oracle.reduce({"fn": "product"}, x[xo:xo + n], z[zo:zo + n])["exact"]
+        assert r == ref, (xo, zo)  # integer-valued partial sums below 2^24 are exact in any order
+
+
+@pytest.mark.parametrize("name", list(INT_FNS))
+def test_int_sum_bit_exact(name):
+    for n in SIZES:
+        x = make_x(n, torch.int32, seed=n + 6)
+        r = hdc.transform_reduce(x.to(gpu()), INT_FNS[name], "exact_int").item()
+        assert r == oracle.reduce(INT_FNS[name], x)["isum"], (name, n)
+    # wrap mod 2^64
+    x = torch.full((4096,), 2 ** 31 - 1, dtype=torch.int32)
+    fn = {"fn": "affine", "a": 1 << 40, "b": 0}
+    assert hdc.transform_reduce(x.to(gpu()), fn, "exact_int").item() == oracle.reduce(fn, x)["isum"]
+
+
+def test_arithmetic_series_int():
+    for n in [1 << 16, (1 << 20) + 7]:
+        x = torch.arange(n, dtype=torch.int32)
+        assert hdc.transform_reduce(x.to(gpu()), {"fn": "identity"}, "exact_int").item() == n * (n - 1) // 2
+
+
+def test_sums_exact_in_any_order():
+    # integers in [0, 15] (partial sums < 2^24) and 2^-i: exact regardless of association
+    xi = synth.uniform_int(3, 0, 1 << 20, bits=4).float()
+    assert hdc.transform_reduce(xi.to(gpu()), {"fn": "identity"}).item() == float(xi.double().sum())
+    for n in range(1, 25):
+        x = torch.tensor([2.0 ** -i for i in range(n)])
+        assert hdc.transform_reduce(x.to(gpu()), {"fn": "identity"}).item() == 2.0 - 2.0 ** (1 - n)
+
+
+def test_compensated_textbook_all_orders():
+    for perm in itertools.permutations([1.0, 1e8, -1e8]):
+        x = torch.tensor(perm, dtype=torch.float32).to(gpu())
+        assert hdc.transform_reduce(x, {"fn": "identity"}, "compensated").item() == 1.0
+
+
+def test_compensated_recovers_ill_conditioned_sum():
+    for dt in (torch.bfloat16, torch.float16):
+        v, info = synth.ill_conditioned(synth.seed_of(3), 1 << 20, dt)
+        g = v.to(gpu())
+        comp = hdc.transform_reduce(g, {"fn": "identity"}, "compensated").item()
+        plain = hdc.transform_reduce(g, {"fn": "identity"}, "plain").item()
+        t = info["target"]
+        assert abs(comp - t) <= 1e-6 * info["abs_sum"]
+        assert abs(comp - t) <= 1e-2 * abs(t)          # digits survive at kappa ~ 1e8
+        assert abs(plain - t) <= 1e-6 * info["abs_sum"]  # the plain sum only meets the sum|x| gate
+
+
+def test_nonfinite_propagates():
+    x = torch.zeros(100000)
+    x[777] = math.inf
+    g = x.to(gpu())
+    assert hdc.transform_reduce(g, {"fn": "identity"}, "plain").item() == math.inf
+    assert hdc.transform_reduce(g, {"fn": "identity"}, "compensated").item() == math.inf
+    x[99999] = -math.inf
+    g = x.to(gpu())
+    assert math.isnan(hdc.transform_reduce(g, {"fn": "identity"}, "compensated").item())
+
+
+def test_deterministic_bits():
+    x = synth.to_storage(synth.normal_f64(8, 0, (1 << 22) + 11), torch.float32).to(gpu())
+    for acc in ("plain", "compensated"):
+        a = hdc.transform_reduce(x, FNS["horner"], acc)
+        b = hdc.transform_reduce(x, FNS["horner"], acc)
+        assert torch.equal(a, b)
+
+
+def test_tuning_variants_stay_within_tolerance():
+    n = (1 << 21) + 13
+    x = make_x(n, torch.float32, seed=21)
+    ref = oracle.reduce(FNS["horner"], x)
+    g = x.to(gpu())
+    b = hdc.tuning_bucket(n)
+    old = hdc.get_tuning(hdc.OP_TRANSFORM_REDUCE, hdc.F32, hdc.ACC_PLAIN, b)
+    try:
+        for block, unroll, gm in [(64, 1, 1), (128, 2, 3), (512, 8, 16), (1024, 4, 64), (256, 8, 2)]:
+            hdc.set_tuning(hdc.OP_TRANSFORM_REDUCE, hdc.F32, hdc.ACC_PLAIN, b, block=block, unroll=unroll,
+                           grid_mult=gm)
+            assert_close_sum(hdc.transform_reduce(g, FNS["horner"]).item(), ref, str((block, unroll, gm)))
+    finally:
+        hdc.set_tuning(hdc.OP_TRANSFORM_REDUCE, hdc.F32, hdc.ACC_PLAIN, b, **old)
+
+
+def test_library_workspace_when_none_passed():
+    x = make_x(50000, torch.float32, seed=4).to(gpu())
+    r = torch.empty((), dtype=torch.float32, device=gpu())
+    f = hdc.make_functor(FNS["identity"])
+    import ctypes
+    st = hdc.lib().hdc_transform_reduce(ctypes.byref(f), hdc.F32, x.data_ptr(), None, x.numel(), 0,
+                                        r.data_ptr(), None, 0, torch.cuda.current_stream().cuda_stream)
+    assert st == hdc.OK
+    assert_close_sum(r.item(), oracle.reduce(FNS["identity"], x.cpu()))
+
+
+# --------------------------------------------------------------------------
+# fused map + reduce
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dt", FLOAT_DTYPES + [torch.int32])
+def test_map_reduce_fused(dt):
+    if dt == torch.int32:
+        mf, rf, acc = INT_FNS["affine"], INT_FNS["identity"], "exact_int"
+    else:
+        mf, rf, acc = FNS["affine"], FNS["horner"], "compensated"
+    for n in [0, 5, 1000, 65541, (1 << 20) + 3]:
+        x = make_x(n, dt, seed=n + 8)
+        y, r = hdc.map_reduce(x.to(gpu()), mf, rf, acc)
+        assert torch.equal(bits(y.cpu()), bits(oracle.map(mf, x)))
+        ref = oracle.reduce(rf, x)
+        if dt == torch.int32:
+            assert r.item() == ref["isum"]
+        else:
+            assert_close_sum(r.item(), ref, f"fused {dt} n={n}")

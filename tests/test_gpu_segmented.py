@@ -1,0 +1,142 @@
+"""GPU parity of hdc_segmented_reduce against the CPU oracle, through the C ABI.
+
+Per segment: integers bit-exact; floating point within 1e-6 * sum|terms| of
+that segment's exact sum (exactly 0 for empty or all-zero segments).
+"""
+import zlib
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2309_03912_amd as hdc
+import synth
+
+pytestmark = pytest.mark.gpu
+
+COEF8 = synth.horner_coefficients(8)
+FNS = {
+    "identity": {"fn": "identity"},
+    "affine": {"fn": "affine", "a": 2.5, "b": 0.5},
+    "horner": {"fn": "horner", "coef": COEF8},
+}
+FLOAT_DTYPES = [torch.float32, torch.float16, torch.bfloat16]
+TOL = 1e-6
+
+
+def gpu():
+    return torch.device("cuda", 0)
+
+
+def edge_lengths(seed=0, count=600):
+    """Lengths that straddle every class boundary of the default tuning
+    (small <= 128 packed, pieces of 4096) plus random ones."""
+    rng = np.random.default_rng(seed)
+    special = [0, 0, 1, 2, 7, 8, 9, 63, 64, 65, 127, 128, 129, 130, 1000, 4095, 4096, 4097, 8191, 8192, 8193,
+               3 * 4096, 3 * 4096 + 5, 20000, 0, 1, 70000]
+    rand = rng.integers(0, 3000, count - len(special)).tolist()
+    L = special + rand
+    rng.shuffle(L)
+    return torch.tensor(L, dtype=torch.int64)
+
+
+def check_segments(got, ref, what):
+    got = got.cpu().double().numpy()
+    exact, A = ref["exact"], ref["abs_sum"]
+    err = np.abs(got - exact)
+    bad = np.where(err > TOL * A)[0]
+    assert bad.size == 0, f"{what}: {bad.size} segments off, first {bad[:5]} got {got[bad[:3]]} exact {exact[bad[:3]]}"
+    zero = A == 0
+    assert np.all(got[zero] == 0.0), what
+
+
+@pytest.mark.parametrize("acc", ["plain", "compensated"])
+@pytest.mark.parametrize("dt", FLOAT_DTYPES)
+@pytest.mark.parametrize("name", list(FNS))
+def test_segmented_float_edges(acc, dt, name):
+    L = edge_lengths(seed=zlib.crc32(f"{acc}{dt}{name}".encode()) % 1000)
+    off = synth.offsets_from_lengths(L)
+    n = int(off[-1])
+    x = synth.to_storage(synth.uniform_pm1_f32(7, 0, n).double(), dt)
+    r = hdc.segmented_reduce(x.to(gpu()), off.to(gpu()), FNS[name], acc)
+    check_segments(r, oracle.segmented(FNS[name], x, off), f"{name} {dt} {acc}")
+
+
+@pytest.mark.parametrize("name", ["identity", "affine"])
+def test_segmented_int_bit_exact(name):
+    fn = {"fn": "identity"} if name == "identity" else {"fn": "affine", "a": 3, "b": -7}
+    L = edge_lengths(seed=3)
+    off = synth.offsets_from_lengths(L)
+    x = synth.uniform_int(8, 10, int(off[-1]))
+    r = hdc.segmented_reduce(x.to(gpu()), off.to(gpu()), fn, "exact_int")
+    assert np.array_equal(r.cpu().numpy(), oracle.segmented(fn, x, off)["isum"])
+
+
+def test_segmented_single_and_empty():
+    x = synth.uniform_pm1_f32(1, 0, 123457)
+    g = x.to(gpu())
+    off = torch.tensor([0, 123457])
+    r = hdc.segmented_reduce(g, off.to(gpu()), FNS["horner"], "compensated")
+    check_segments(r, oracle.segmented(FNS["horner"], x, off), "single")
+    off = torch.zeros(1001, dtype=torch.int64)
+    r = hdc.segmented_reduce(g, off.to(gpu()), FNS["horner"], "plain")
+    assert torch.equal(r.cpu(), torch.zeros(1000))
+    r = hdc.segmented_reduce(g, torch.zeros(1, dtype=torch.int64, device=gpu()), FNS["horner"], "plain")
+    assert r.numel() == 0
+
+
+def test_segmented_offset_base_and_misaligned_x():
+    # offsets need not start at 0; x may be an unaligned view
+    base = synth.uniform_pm1_f32(2, 0, 600003)
+    g = base.to(gpu())[3:]
+    xs = base[3:]
+    L = edge_lengths(seed=5, count=100)
+    off = synth.offsets_from_lengths(L) + 11
+    r = hdc.segmented_reduce(g, off.to(gpu()), FNS["affine"], "plain")
+    check_segments(r, oracle.segmented(FNS["affine"], xs, off), "offset base")
+
+
+def test_segmented_tuning_variants():
+    L = edge_lengths(seed=9, count=400)
+    off = synth.offsets_from_lengths(L)
+    n = int(off[-1])
+    x = synth.uniform_pm1_f32(3, 0, n)
+    ref = oracle.segmented(FNS["horner"], x, off)
+    g, og = x.to(gpu()), off.to(gpu())
+    b = hdc.tuning_bucket(n)
+    old = hdc.get_tuning(hdc.OP_SEGMENTED_REDUCE, hdc.F32, hdc.ACC_PLAIN, b)
+    try:
+        for chunk, small, spw, block, unroll, gm in [(1024, 1, 1, 64, 1, 1), (2048, 64, 64, 128, 2, 2),
+                                                      (16384, 1024, 2, 1024, 8, 4), (65536, 256, 16, 256, 4, 64),
+                                                      (4096, 128, 8, 512, 8, 16)]:
+            hdc.set_tuning(hdc.OP_SEGMENTED_REDUCE, hdc.F32, hdc.ACC_PLAIN, b, block=block, unroll=unroll,
+                           grid_mult=gm, chunk=chunk, small_seg=small, seg_per_wave=spw)
+            r = hdc.segmented_reduce(g, og, FNS["horner"], "plain")
+            check_segments(r, ref, str((chunk, small, spw, block, unroll, gm)))
+    finally:
+        hdc.set_tuning(hdc.OP_SEGMENTED_REDUCE, hdc.F32, hdc.ACC_PLAIN, b, **old)
+
+
+def test_segmented_deterministic():
+    L = synth.segment_lengths(11, 20000, total_target=2.0 ** 24)
+    off = synth.offsets_from_lengths(L)
+    x = synth.uniform_pm1_f32(11, 0, int(off[-1])).to(gpu())
+    og = off.to(gpu())
+    for acc in ("plain", "compensated"):
+        a = hdc.segmented_reduce(x, og, FNS["horner"], acc)
+        b = hdc.segmented_reduce(x, og, FNS["horner"], acc)
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("acc", ["plain", "compensated"])
+def test_segmented_full_lognormal_workload(acc):
+    """100,000 lognormal segments (median 256, max 2^20, ~2^27 elements)."""
+    seed = synth.seed_of(4)
+    L = synth.segment_lengths(seed)
+    off = synth.offsets_from_lengths(L)
+    n = int(off[-1])
+    xg = synth.uniform_pm1_f32(seed, synth.STREAM["x"], n, gpu())
+    r = hdc.segmented_reduce(xg, off.to(gpu()), FNS["horner"], acc)
+    torch.cuda.synchronize()
+    check_segments(r, oracle.segmented(FNS["horner"], xg.cpu(), off), f"lognormal {acc}")
