@@ -20,6 +20,9 @@ import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhdc.so")
+# Tuning cache written by the autotuner for gfx950; loaded with the library
+# unless HDC_TUNE_CACHE names another one.
+TUNING_CACHE = os.path.join(HERE, "tuning_gfx950.txt")
 
 # C enums (hdc.h)
 OK, ERR_INVALID_ARGUMENT, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP = range(5)
@@ -98,6 +101,8 @@ def lib() -> ctypes.CDLL:
         L.hdc_version.argtypes = []
         L.hdc_version.restype = ctypes.c_int32
         _lib = L
+        if not os.environ.get("HDC_TUNE_CACHE") and os.path.exists(TUNING_CACHE):
+            _check(L.hdc_load_tuning(TUNING_CACHE.encode()))
     return _lib
 
 

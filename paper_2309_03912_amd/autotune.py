@@ -1,0 +1,245 @@
+"""Autotuner of the library's launch parameters.
+
+For each tuning class (op, dtype, accumulation, size bucket) it times every
+candidate setting of (block, unroll, grid_mult) -- and, for the segmented op,
+(chunk, small_seg, seg_per_wave) -- on a synthetic workload of that class:
+
+  * HIP events on the launching stream, `reps` calls per measurement, median
+    of `rounds` measurements; candidates are interleaved round by round so
+    that clock or thermal drift hits all of them alike;
+  * the best three are re-timed with twice the rounds before one is chosen;
+  * every candidate's output must agree with the others: maps bit for bit,
+    integer sums exactly, floating-point sums within the library tolerance
+    (1e-6 of the sum of magnitudes; the tuning workloads have positive terms,
+    so that is 1e-6 of the result).
+
+The winners are written as a tuning cache (one line per class:
+"op dtype acc bucket block unroll grid_mult chunk small_seg seg_per_wave"),
+which the library reads through hdc_load_tuning / HDC_TUNE_CACHE.
+
+    python -m paper_2309_03912_amd.autotune --out paper_2309_03912_amd/tuning_gfx950.txt
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import os
+import statistics
+import sys
+import time
+
+import torch
+
+from . import (ACC_COMPENSATED, ACC_EXACT_INT, ACC_PLAIN, BF16, F16, F32, I32, OP_MAP, OP_MAP_REDUCE,
+               OP_SEGMENTED_REDUCE, OP_TRANSFORM_REDUCE, get_tuning, set_tuning, tuning_bucket)
+from . import map as hdc_map
+from . import map_reduce, segmented_reduce, transform_reduce, workspace
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_CACHE = os.path.join(HERE, "tuning_gfx950.txt")
+TORCH_DT = {F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16, I32: torch.int32}
+FIELDS = ["block", "unroll", "grid_mult", "chunk", "small_seg", "seg_per_wave"]
+
+
+def _inputs(dt, n, dev, seed=1):
+    """Positive-term tuning data: U[-1, 1) for floats (p(x) > 0 there), U[0, 2^20) ints."""
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    if dt == I32:
+        return torch.randint(0, 1 << 20, (n,), generator=g, dtype=torch.int32).to(dev)
+    x = (torch.randint(0, 1 << 24, (n,), generator=g, dtype=torch.int64) - (1 << 23)).to(torch.float32)
+    return (x * 2.0 ** -23).to(TORCH_DT[dt]).to(dev)
+
+
+def _time(fn, reps):
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    e.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+class Case:
+    """One tuning class with its workload and a runner returning the output."""
+
+    def __init__(self, op, dt, acc, n, dev, segments=None):
+        self.op, self.dt, self.acc, self.n = op, dt, acc, n
+        self.bucket = tuning_bucket(n)
+        self.x = _inputs(dt, n, dev)
+        coef = [1.0 / (k + 1) for k in range(9)]
+        self.horner = {"fn": "horner", "coef": coef}
+        self.aff = {"fn": "affine", "a": 3, "b": -7} if dt == I32 else {"fn": "affine", "a": 2.5, "b": 0.5}
+        self.ident = {"fn": "identity"}
+        self.y = torch.empty_like(self.x)
+        accname = {ACC_PLAIN: "plain", ACC_COMPENSATED: "compensated", ACC_EXACT_INT: "exact_int"}[acc]
+        self.accname = accname
+        if op == OP_SEGMENTED_REDUCE:
+            self.off = segments.to(dev)
+            S = self.off.numel() - 1
+            self.ws = workspace(dev, op, dt, acc, n, S)
+            self.out = torch.empty(S, dtype={ACC_PLAIN: torch.float32, ACC_COMPENSATED: torch.float64,
+                                             ACC_EXACT_INT: torch.int64}[acc], device=dev)
+        elif op != OP_MAP:
+            self.ws = workspace(dev, op, dt, acc, n)
+            self.out = torch.empty((), dtype={ACC_PLAIN: torch.float32, ACC_COMPENSATED: torch.float64,
+                                              ACC_EXACT_INT: torch.int64}[acc], device=dev)
+        if op == OP_TRANSFORM_REDUCE and dt != I32:
+            self.z = _inputs(dt, n, dev, seed=2)
+
+    def run(self):
+        if self.op == OP_MAP:
+            hdc_map(self.x, self.aff, out=self.y)
+        elif self.op == OP_TRANSFORM_REDUCE:
+            fn = self.ident if self.dt == I32 else self.horner
+            transform_reduce(self.x, fn, self.accname, out=self.out, ws=self.ws)
+        elif self.op == OP_MAP_REDUCE:
+            fn = self.ident if self.dt == I32 else self.horner
+            map_reduce(self.x, self.aff, fn, self.accname, out=self.y, result=self.out, ws=self.ws)
+        else:
+            fn = self.ident if self.dt == I32 else self.horner
+            segmented_reduce(self.x, self.off, fn, self.accname, out=self.out, ws=self.ws)
+
+    def run_dot(self):
+        transform_reduce(self.x, {"fn": "product"}, self.accname, z=self.z, out=self.out, ws=self.ws)
+
+    def output(self):
+        if self.op == OP_MAP:
+            return self.y.clone()
+        if self.op == OP_MAP_REDUCE:
+            return (self.y.clone(), self.out.clone())
+        return self.out.clone()
+
+    def agrees(self, a, b):
+        if self.op == OP_MAP:
+            return torch.equal(a.view(torch.int16) if a.element_size() == 2 else a.view(torch.int32),
+                               b.view(torch.int16) if b.element_size() == 2 else b.view(torch.int32))
+        if self.op == OP_MAP_REDUCE:
+            return self.agrees_map(a[0], b[0]) and self.agrees_sum(a[1], b[1])
+        return self.agrees_sum(a, b)
+
+    def agrees_map(self, a, b):
+        return torch.equal(a.view(torch.int16) if a.element_size() == 2 else a.view(torch.int32),
+                           b.view(torch.int16) if b.element_size() == 2 else b.view(torch.int32))
+
+    def agrees_sum(self, a, b):
+        if self.acc == ACC_EXACT_INT:
+            return torch.equal(a, b)
+        a, b = a.double(), b.double()
+        return bool(((a - b).abs() <= 2e-6 * torch.maximum(a.abs(), b.abs()) + 1e-30).all())
+
+    def key(self):
+        return (self.op, self.dt, self.acc, self.bucket)
+
+
+def candidates(op, quick=False):
+    blocks = [256, 512, 1024] if quick else [128, 256, 512, 1024]
+    unrolls = [2, 4, 8] if quick else [1, 2, 4, 8]
+    gms = [4, 8, 16] if quick else [2, 4, 8, 16, 32]
+    base = [dict(block=b, unroll=u, grid_mult=g) for b, u, g in itertools.product(blocks, unrolls, gms)]
+    if op != OP_SEGMENTED_REDUCE:
+        return base
+    seg = [dict(chunk=c, small_seg=s, seg_per_wave=w)
+           for c, s, w in itertools.product([2048, 4096, 8192] if quick else [1024, 2048, 4096, 8192, 16384],
+                                            [64, 128, 256], [4, 8, 16])]
+    # two stages: geometry at the default segment split, then the split at the best geometry
+    return base, seg
+
+
+def tune_case(case: Case, quick=False, reps=5, rounds=3, log=print):
+    op, dt, acc, b = case.key()
+    cands = candidates(op, quick)
+    stages = [cands] if op != OP_SEGMENTED_REDUCE else list(cands)
+    best = get_tuning(op, dt, acc, b)
+    for stage in stages:
+        trial = [dict(best, **c) for c in stage]
+        times = {i: [] for i in range(len(trial))}
+        ref = None
+        for r in range(rounds):
+            order = list(range(len(trial))) if r % 2 == 0 else list(reversed(range(len(trial))))
+            for i in order:
+                set_tuning(op, dt, acc, b, **trial[i])
+                case.run()
+                if r == 0:
+                    out = case.output()
+                    if ref is None:
+                        ref = out
+                    elif not case.agrees(ref, out):
+                        raise RuntimeError(f"candidate {trial[i]} disagrees with {trial[0]} on {case.key()}")
+                t = _time(case.run, reps)
+                if op == OP_TRANSFORM_REDUCE and dt != I32:
+                    t += _time(case.run_dot, reps)  # the class also serves dot products
+                times[i].append(t)
+        med = {i: statistics.median(v) for i, v in times.items()}
+        top = sorted(med, key=med.get)[:3]
+        re = {i: [] for i in top}
+        for r in range(2 * rounds):
+            for i in top:
+                set_tuning(op, dt, acc, b, **trial[i])
+                t = _time(case.run, reps)
+                if op == OP_TRANSFORM_REDUCE and dt != I32:
+                    t += _time(case.run_dot, reps)
+                re[i].append(t)
+        win = min(top, key=lambda i: statistics.median(re[i]))
+        best = trial[win]
+        set_tuning(op, dt, acc, b, **best)
+        log(json.dumps({"class": case.key(), "n": case.n, "best": best,
+                        "ms": round(statistics.median(re[win]), 5),
+                        "default_ms": round(med[0], 5), "candidates": len(trial)}))
+    return best
+
+
+def default_cases(dev, quick=False, log2n=28):
+    """The classes the workloads of this project use, at their sizes."""
+    import synth  # seeded generators of the workloads (segment lengths)
+    n = 1 << log2n
+    cases = [
+        Case(OP_MAP, F32, ACC_PLAIN, n, dev),
+        Case(OP_MAP, I32, ACC_PLAIN, n, dev),
+        Case(OP_TRANSFORM_REDUCE, F32, ACC_PLAIN, n, dev),
+        Case(OP_TRANSFORM_REDUCE, I32, ACC_EXACT_INT, n, dev),
+        Case(OP_TRANSFORM_REDUCE, BF16, ACC_COMPENSATED, n, dev),
+        Case(OP_TRANSFORM_REDUCE, F16, ACC_COMPENSATED, n, dev),
+        Case(OP_TRANSFORM_REDUCE, F32, ACC_COMPENSATED, n, dev),
+    ]
+    L = synth.segment_lengths(synth.seed_of(4))
+    off = synth.offsets_from_lengths(L)
+    cases += [Case(OP_SEGMENTED_REDUCE, F32, ACC_PLAIN, int(off[-1]), dev, off),
+              Case(OP_SEGMENTED_REDUCE, F32, ACC_COMPENSATED, int(off[-1]), dev, off)]
+    # batched calls: every size bucket of the fused map + reduce
+    for m in ([1 << 14, 1 << 18, 1 << 22, 1 << 25] if not quick else [1 << 18, 1 << 25]):
+        cases += [Case(OP_MAP_REDUCE, F16, ACC_COMPENSATED, m, dev), Case(OP_MAP_REDUCE, I32, ACC_EXACT_INT, m, dev),
+                  Case(OP_MAP, F16, ACC_PLAIN, m, dev), Case(OP_TRANSFORM_REDUCE, F16, ACC_COMPENSATED, m, dev)]
+    return cases
+
+
+def write_cache(path, results):
+    lines = ["# hdc tuning cache (gfx950): op dtype acc bucket block unroll grid_mult chunk small_seg seg_per_wave"]
+    for (op, dt, acc, b), t in sorted(results.items()):
+        lines.append(" ".join(str(v) for v in (op, dt, acc, b, *(t[f] for f in FIELDS))))
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def main(argv=None):
+    p = argparse.ArgumentParser(description=__doc__)
+    p.add_argument("--out", default=DEFAULT_CACHE)
+    p.add_argument("--quick", action="store_true")
+    p.add_argument("--log2n", type=int, default=28)
+    a = p.parse_args(argv)
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    results = {}
+    for case in default_cases(dev, a.quick, a.log2n):
+        results[case.key()] = tune_case(case, a.quick, log=lambda s: print(s, flush=True))
+        del case
+        torch.cuda.empty_cache()
+    write_cache(a.out, results)
+    print(json.dumps({"written": a.out, "classes": len(results), "seconds": round(time.time() - t0, 1)}),
+          flush=True)
+
+
+if __name__ == "__main__":
+    sys.exit(main())
