@@ -406,6 +406,40 @@ def form_graph(args, torch, hdc, synth):
             nb = bytes_fused if fused else bytes_sep
             key = ("fused" if fused else "separate") + f"_graph_{branches}branch"
             res[key] = {"ms_per_replay": round(ms, 4), "GBps": round(gbps(nb, ms), 1)}
+    # grouped batch: the 32 fp16 calls in one grouped launch, the 32 int32 calls in another
+    h_calls = [c for c in calls if c["kind"] == "fp16"]
+    i_calls = [c for c in calls if c["kind"] == "i32"]
+    wsb = [torch.zeros(hdc.workspace_size(hdc.OP_BATCH, dtc, accc, sum(c["n"] for c in cl), len(cl)),
+                       dtype=torch.uint8, device=dev)
+           for dtc, accc, cl in ((hdc.F16, hdc.ACC_COMPENSATED, h_calls), (hdc.I32, hdc.ACC_EXACT_INT, i_calls))]
+
+    def grouped():
+        hdc.batch_map_reduce([c["x"] for c in h_calls], faff, hor, "compensated", ys=[c["y"] for c in h_calls],
+                             outs=[c["r"] for c in h_calls], ws=wsb[0])
+        hdc.batch_map_reduce([c["x"] for c in i_calls], iaff, iid, "exact_int", ys=[c["y"] for c in i_calls],
+                             outs=[c["r"] for c in i_calls], ws=wsb[1])
+    grouped()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = max(5, args.replays // 4)
+    for _ in range(reps):
+        grouped()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    res["grouped_eager"] = {"ms_per_replay": round(ms, 4), "GBps": round(gbps(bytes_fused, ms), 1)}
+    gg = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gg, stream=torch.cuda.Stream(device=dev)):
+        grouped()
+    torch.cuda.synchronize()
+    gg.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.replays):
+        gg.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.replays
+    res["grouped_graph"] = {"ms_per_replay": round(ms, 4), "GBps": round(gbps(bytes_fused, ms), 1)}
+
     # eager plain-FP32 comparator (f32 storage for the fp16 calls)
     def eager_f32():
         for i in order:

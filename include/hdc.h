@@ -84,7 +84,8 @@ typedef enum hdc_op {
   HDC_OP_MAP = 0,
   HDC_OP_TRANSFORM_REDUCE = 1,
   HDC_OP_SEGMENTED_REDUCE = 2,
-  HDC_OP_MAP_REDUCE = 3
+  HDC_OP_MAP_REDUCE = 3,
+  HDC_OP_BATCH = 4
 } hdc_op;
 
 #define HDC_MAX_DEGREE 16
@@ -151,7 +152,35 @@ hdc_status hdc_map_reduce(const hdc_functor* f, const hdc_functor* g,
                           hdc_accum acc, void* out, void* workspace,
                           size_t ws_bytes, void* stream);
 
-/* Bytes of workspace `op` needs for these sizes (0 for HDC_OP_MAP). */
+/* One call of a grouped batch (device pointers). */
+typedef struct hdc_batch_call {
+  const void* x;
+  void* y;        /* map output, or NULL: this call only folds */
+  int64_t n;
+  void* out;      /* one float / double / int64, as the accumulation says */
+} hdc_batch_call;
+
+/*
+ * Many independent calls of one class -- same dtype, map callable f, fold
+ * callable g and accumulation -- in one grouped launch plus one combine
+ * launch per 32 calls: y = f(x) (when f and the call's y are non-NULL) and
+ * *out = the fold of g over x, each call exactly as hdc_map_reduce /
+ * hdc_transform_reduce define it.  `calls` is a HOST array read during this
+ * call (the table is passed to the kernels by value, so the launches can be
+ * recorded into a graph).  A call whose x and y differ in 16-byte alignment
+ * runs on its own.  Workspace: hdc_workspace_size(HDC_OP_BATCH, dt, acc,
+ * sum of n, count, ...).  Reduction results depend on the tuning of
+ * HDC_OP_BATCH (chunk length), not on the batch composition.
+ */
+hdc_status hdc_batch_map_reduce(const hdc_functor* f, const hdc_functor* g,
+                                hdc_dtype dt, hdc_accum acc,
+                                const hdc_batch_call* calls, int32_t count,
+                                void* workspace, size_t ws_bytes,
+                                void* stream);
+
+/* Bytes of workspace `op` needs for these sizes (0 for HDC_OP_MAP).  For
+ * HDC_OP_SEGMENTED_REDUCE, n is `total` and num_segments is S; for
+ * HDC_OP_BATCH, n is the sum of the calls' n and num_segments the count. */
 hdc_status hdc_workspace_size(int op, hdc_dtype dt, hdc_accum acc, int64_t n,
                               int64_t num_segments, size_t* bytes);
 

@@ -29,7 +29,7 @@ OK, ERR_INVALID_ARGUMENT, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP = range(5)
 F32, F16, BF16, I32, I64, F64 = range(6)
 FN_IDENTITY, FN_AFFINE, FN_HORNER, FN_PRODUCT = range(4)
 ACC_PLAIN, ACC_COMPENSATED, ACC_EXACT_INT = range(3)
-OP_MAP, OP_TRANSFORM_REDUCE, OP_SEGMENTED_REDUCE, OP_MAP_REDUCE = range(4)
+OP_MAP, OP_TRANSFORM_REDUCE, OP_SEGMENTED_REDUCE, OP_MAP_REDUCE, OP_BATCH = range(5)
 MAX_DEGREE = 16
 
 DTYPE = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16, torch.int32: I32}
@@ -39,7 +39,7 @@ FN = {"identity": FN_IDENTITY, "affine": FN_AFFINE, "horner": FN_HORNER, "produc
 
 # Every symbol include/hdc.h declares.
 EXPORTS = [
-    "hdc_map", "hdc_transform_reduce", "hdc_segmented_reduce", "hdc_map_reduce",
+    "hdc_map", "hdc_transform_reduce", "hdc_segmented_reduce", "hdc_map_reduce", "hdc_batch_map_reduce",
     "hdc_workspace_size", "hdc_validate_offsets", "hdc_set_tuning", "hdc_get_tuning",
     "hdc_load_tuning", "hdc_tuning_bucket", "hdc_status_string", "hdc_last_error", "hdc_version",
 ]
@@ -56,6 +56,10 @@ class Tuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("unroll", ctypes.c_int32),
                 ("grid_mult", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("small_seg", ctypes.c_int32), ("seg_per_wave", ctypes.c_int32)]
+
+
+class BatchCall(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("n", ctypes.c_int64), ("out", ctypes.c_void_p)]
 
 
 class HdcError(RuntimeError):
@@ -84,6 +88,8 @@ def lib() -> ctypes.CDLL:
         L.hdc_transform_reduce.argtypes = [P(Functor), i32, vp, vp, i64, i32, vp, vp, ctypes.c_size_t, vp]
         L.hdc_segmented_reduce.argtypes = [P(Functor), i32, vp, vp, i64, i64, i32, vp, vp, ctypes.c_size_t, vp]
         L.hdc_map_reduce.argtypes = [P(Functor), P(Functor), i32, vp, vp, i64, i32, vp, vp, ctypes.c_size_t, vp]
+        L.hdc_batch_map_reduce.argtypes = [P(Functor), P(Functor), i32, i32, P(BatchCall), ctypes.c_int32, vp,
+                                           ctypes.c_size_t, vp]
         L.hdc_workspace_size.argtypes = [i32, i32, i32, i64, i64, P(ctypes.c_size_t)]
         L.hdc_validate_offsets.argtypes = [vp, i64, i64, vp]
         L.hdc_set_tuning.argtypes = [i32, i32, i32, i32, P(Tuning)]
@@ -91,6 +97,7 @@ def lib() -> ctypes.CDLL:
         L.hdc_tuning_bucket.argtypes = [i64, P(ctypes.c_int32)]
         L.hdc_load_tuning.argtypes = [ctypes.c_char_p]
         for name in ["hdc_map", "hdc_transform_reduce", "hdc_segmented_reduce", "hdc_map_reduce",
+                     "hdc_batch_map_reduce",
                      "hdc_workspace_size", "hdc_validate_offsets", "hdc_set_tuning", "hdc_get_tuning",
                      "hdc_load_tuning", "hdc_tuning_bucket"]:
             getattr(L, name).restype = st
@@ -272,6 +279,38 @@ def segmented_reduce(x: torch.Tensor, offsets: torch.Tensor, fn, acc="plain", to
     _check(lib().hdc_segmented_reduce(ctypes.byref(f), dt, x.data_ptr(), offsets.data_ptr(), S, total, a,
                                       r.data_ptr(), ws.data_ptr(), ws.numel(), _stream(x)))
     return r
+
+
+def batch_map_reduce(xs, map_fn, reduce_fn, acc="plain", ys=None, outs=None, ws=None):
+    """Grouped form of many map_reduce calls of one class: ys[i] = map_fn(xs[i])
+    (skipped when map_fn is None or ys[i] is None) and outs[i] = the fold of
+    reduce_fn over xs[i].  Returns (ys, outs)."""
+    if not xs:
+        return [], []
+    a = _acc(acc)
+    dt = _dtype(xs[0])
+    dev = xs[0].device
+    if ys is None:
+        ys = [torch.empty_like(x) for x in xs] if map_fn is not None else [None] * len(xs)
+    if outs is None:
+        outs = [torch.empty((), dtype=OUT_DTYPE[a], device=dev) for _ in xs]
+    table = (BatchCall * len(xs))()
+    for i, x in enumerate(xs):
+        _gpu_tensor(x, "x")
+        if _dtype(x) != dt:
+            raise ValueError("all calls of a batch share one dtype")
+        y = ys[i]
+        table[i].x = x.data_ptr()
+        table[i].y = y.data_ptr() if (y is not None and map_fn is not None) else None
+        table[i].n = x.numel()
+        table[i].out = outs[i].data_ptr()
+    if ws is None:
+        ws = workspace(dev, OP_BATCH, dt, a, sum(x.numel() for x in xs), len(xs))
+    f = ctypes.byref(make_functor(map_fn)) if map_fn is not None else None
+    g = make_functor(reduce_fn)
+    _check(lib().hdc_batch_map_reduce(f, ctypes.byref(g), dt, a, table, len(xs), ws.data_ptr(), ws.numel(),
+                                      _stream(xs[0])))
+    return ys, outs
 
 
 def validate_offsets(offsets: torch.Tensor, total: int) -> None:

@@ -1,5 +1,6 @@
-// Host side of the library: argument checks, the functor-id -> concrete type
-// dispatch, launch geometry, workspaces, tuning, and the C ABI of hdc.h.
+// Host side of the library: the C ABI of hdc.h, argument checks, workspaces
+// and tuning.  The functor-id -> concrete type dispatch and the launches live
+// in the per-family translation units (hdc_run_*.hip).
 //
 // The dispatch is the paper's "deduce the execution space from the argument
 // type" (section 2.10, "SFINAE 3 with macro") moved to a runtime boundary: a
@@ -18,18 +19,20 @@
 #include <utility>
 
 #include "hdc.h"
-#include "hdc_kernels.hpp"
-#include "hdc_segmented.hpp"
+#include "hdc_batch.hpp"
+#include "hdc_host.hpp"
 
 using namespace hdc;
 
+namespace hdc {
+
+// ---------------------------------------------------------------------------
+// Errors and device facts (shared with the launcher translation units)
+// ---------------------------------------------------------------------------
+
 namespace {
-
-// ---------------------------------------------------------------------------
-// Errors
-// ---------------------------------------------------------------------------
-
 thread_local char g_last_error[512] = "";
+}  // namespace
 
 hdc_status fail(hdc_status s, const char* fmt, ...) {
   va_list ap;
@@ -39,26 +42,36 @@ hdc_status fail(hdc_status s, const char* fmt, ...) {
   return s;
 }
 
-hdc_status check_launch(const char* what) {
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return fail(HDC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+
+namespace {
+constexpr int kMaxDevices = 64;
+int g_cus[kMaxDevices];
+}  // namespace  // 0 = not queried yet
+
+hdc_status compute_units(int* cus) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(HDC_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(HDC_ERR_HIP, "device index %d out of range", dev);
+  if (g_cus[dev] == 0) {
+    int v = 0;
+    e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return fail(HDC_ERR_HIP, "hipDeviceGetAttribute: %s", hipGetErrorString(e));
+    g_cus[dev] = v;
+  }
+  *cus = g_cus[dev];
   return HDC_OK;
 }
+
+}  // namespace hdc
+
+namespace {
 
 // ---------------------------------------------------------------------------
 // Tuning
 // ---------------------------------------------------------------------------
 
-struct Tuning {
-  int block = 256;
-  int unroll = 4;
-  int grid_mult = 8;
-  int chunk = 4096;
-  int small_seg = 128;
-  int seg_per_wave = 8;
-};
-
-constexpr int kOps = 4, kDtypes = 6, kAccs = 3, kBuckets = 4;
+constexpr int kOps = 5, kDtypes = 6, kAccs = 3, kBuckets = 4;
 std::mutex g_tune_mu;
 Tuning g_tune[kOps][kDtypes][kAccs][kBuckets];
 
@@ -123,61 +136,8 @@ Tuning tuning_for(int op, hdc_dtype dt, hdc_accum acc, int64_t n) {
 }
 
 // ---------------------------------------------------------------------------
-// Device facts
-// ---------------------------------------------------------------------------
-
-constexpr int kMaxDevices = 64;
-int g_cus[kMaxDevices];  // 0 = not queried yet
-
-hdc_status compute_units(int* cus) {
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return fail(HDC_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
-  if (dev < 0 || dev >= kMaxDevices) return fail(HDC_ERR_HIP, "device index %d out of range", dev);
-  if (g_cus[dev] == 0) {
-    int v = 0;
-    e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return fail(HDC_ERR_HIP, "hipDeviceGetAttribute: %s", hipGetErrorString(e));
-    g_cus[dev] = v;
-  }
-  *cus = g_cus[dev];
-  return HDC_OK;
-}
-
-// ---------------------------------------------------------------------------
 // Workspaces
 // ---------------------------------------------------------------------------
-
-constexpr int64_t kMaxGrid = 65536;  // upper bound on pass-1 blocks
-constexpr size_t kPartialBytes = 8;  // every fold state fits 8 bytes
-
-size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-size_t reduce_workspace_bytes() { return round_up(kMaxGrid * kPartialBytes, 256); }
-
-constexpr int64_t kMinChunk = 1024;
-
-// Layout of the segmented workspace for a given chunk (sections 256-byte aligned).
-struct SegLayout {
-  size_t cnt, full, part, long_base, long_list, partials, bytes;
-  int64_t cap_full, cap_part, cap_partials;
-};
-
-SegLayout seg_layout(int64_t total, int64_t S, int64_t chunk) {
-  SegLayout l{};
-  l.cap_full = total / chunk + 1;
-  l.cap_part = S > 0 ? S : 1;
-  l.cap_partials = l.cap_full + l.cap_part;
-  size_t o = 0;
-  l.cnt = o;       o += round_up(sizeof(SegCounters), 256);
-  l.full = o;      o += round_up((size_t)l.cap_full * sizeof(SegPiece), 256);
-  l.part = o;      o += round_up((size_t)l.cap_part * sizeof(SegPiece), 256);
-  l.long_base = o; o += round_up((size_t)l.cap_part * sizeof(int32_t), 256);
-  l.long_list = o; o += round_up((size_t)l.cap_part * sizeof(int32_t), 256);
-  l.partials = o;  o += round_up((size_t)l.cap_partials * kPartialBytes, 256);
-  l.bytes = o;
-  return l;
-}
 
 struct InternalWs {
   void* ptr = nullptr;
@@ -280,197 +240,6 @@ hdc_status check_ptr(const void* p, hdc_dtype dt, int64_t n, const char* name) {
   return HDC_OK;
 }
 
-#define HDC_TRY(expr)                 \
-  do {                                \
-    hdc_status s_ = (expr);           \
-    if (s_ != HDC_OK) return s_;      \
-  } while (0)
-
-// ---------------------------------------------------------------------------
-// Functor id -> concrete type; dtype -> storage type
-// ---------------------------------------------------------------------------
-
-template <class Body>
-hdc_status with_float_fn(const hdc_functor& f, Body&& body) {
-  switch (f.id) {
-    case HDC_FN_IDENTITY: return body(Identity{});
-    case HDC_FN_AFFINE: return body(Affine{f.a, f.b});
-    case HDC_FN_HORNER: {
-      Horner h{};
-      h.degree = f.degree;
-      for (int k = 0; k <= f.degree; ++k) h.c[k] = f.coef[k];
-      return body(h);
-    }
-    case HDC_FN_PRODUCT: return body(Product{});
-  }
-  return fail(HDC_ERR_INVALID_ARGUMENT, "unknown functor id %d", f.id);
-}
-
-template <class Body>
-hdc_status with_int_fn(const hdc_functor& f, Body&& body) {
-  switch (f.id) {
-    case HDC_FN_IDENTITY: return body(IntIdentity{});
-    case HDC_FN_AFFINE: return body(IntAffine{f.ia, f.ib});
-  }
-  return fail(HDC_ERR_UNSUPPORTED, "functor %d is not provided for int32", f.id);
-}
-
-template <class Body>
-hdc_status with_float_storage(hdc_dtype dt, Body&& body) {
-  switch (dt) {
-    case HDC_F32: return body(F32{});
-    case HDC_F16: return body(F16{});
-    case HDC_BF16: return body(BF16{});
-    default: return fail(HDC_ERR_UNSUPPORTED, "dtype %d is not floating-point storage", (int)dt);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Geometry
-// ---------------------------------------------------------------------------
-
-template <class S>
-Range make_range(const void* x, int64_t n, bool vector) {
-  Range r{n, 0, 0, 0, 0};
-  if (!vector) return r;
-  const int64_t es = sizeof(typename S::T);
-  const int64_t mis = (int64_t)((uintptr_t)x % 16);
-  int64_t head = mis ? (16 - mis) / es : 0;
-  if (head > n) head = n;
-  r.head = head;
-  r.nvec = (n - head) / S::kVec;
-  r.tail_start = head + r.nvec * S::kVec;
-  r.tail = n - r.tail_start;
-  return r;
-}
-
-int64_t grid_for(int64_t units, int64_t per_block, int cus, const Tuning& t) {
-  int64_t g = (units + per_block - 1) / per_block;
-  int64_t cap = (int64_t)cus * t.grid_mult;
-  if (cap > kMaxGrid) cap = kMaxGrid;
-  if (g > cap) g = cap;
-  if (g < 1) g = 1;
-  return g;
-}
-
-template <class F, class S>
-hdc_status launch_map(const F& f, const void* x, void* y, int64_t n, const Tuning& t, hipStream_t st) {
-  using T = typename S::T;
-  int cus = 0;
-  HDC_TRY(compute_units(&cus));
-  const bool vec = ((uintptr_t)x % 16) == ((uintptr_t)y % 16);
-  Range r = make_range<S>(x, n, vec);
-  const int64_t units = vec ? r.nvec : n;
-  const int64_t g = grid_for(units, (int64_t)t.block * t.unroll, cus, t);
-  auto go = [&](auto U) {
-    constexpr int kU = decltype(U)::value;
-    if (vec)
-      map_kernel<F, S, kU, true><<<dim3((unsigned)g), dim3(t.block), 0, st>>>(f, (const T*)x, (T*)y, r);
-    else
-      map_kernel<F, S, kU, false><<<dim3((unsigned)g), dim3(t.block), 0, st>>>(f, (const T*)x, (T*)y, r);
-  };
-  switch (t.unroll) {
-    case 1: go(std::integral_constant<int, 1>{}); break;
-    case 2: go(std::integral_constant<int, 2>{}); break;
-    case 4: go(std::integral_constant<int, 4>{}); break;
-    default: go(std::integral_constant<int, 8>{}); break;
-  }
-  return check_launch("map kernel launch");
-}
-
-template <class Acc>
-hdc_status launch_final(const Acc* partials, int64_t g, void* out, hipStream_t st) {
-  reduce_final_kernel<Acc><<<dim3(1), dim3(256), 0, st>>>(partials, (int)g, out);
-  return check_launch("final combine launch");
-}
-
-template <class F, class S, class Acc, class FM = Identity, bool kMap = false>
-hdc_status launch_reduce(const F& f, const void* x, const void* z, int64_t n, void* out, void* ws,
-                         const Tuning& t, hipStream_t st, const FM& fm = FM{}, void* y = nullptr) {
-  using T = typename S::T;
-  int cus = 0;
-  HDC_TRY(compute_units(&cus));
-  bool vec = true;
-  if (F::binary && ((uintptr_t)x % 16) != ((uintptr_t)z % 16)) vec = false;
-  if (kMap && ((uintptr_t)x % 16) != ((uintptr_t)y % 16)) vec = false;
-  Range r = make_range<S>(x, n, vec);
-  const int64_t units = vec ? r.nvec : n;
-  const int64_t g = grid_for(units, (int64_t)t.block * t.unroll, cus, t);
-  Acc* partials = static_cast<Acc*>(ws);
-  auto go = [&](auto U) {
-    constexpr int kU = decltype(U)::value;
-    if (vec)
-      reduce_kernel<F, S, Acc, kU, true, FM, kMap><<<dim3((unsigned)g), dim3(t.block), 0, st>>>(
-          f, (const T*)x, (const T*)z, r, partials, fm, (T*)y);
-    else
-      reduce_kernel<F, S, Acc, kU, false, FM, kMap><<<dim3((unsigned)g), dim3(t.block), 0, st>>>(
-          f, (const T*)x, (const T*)z, r, partials, fm, (T*)y);
-  };
-  switch (t.unroll) {
-    case 1: go(std::integral_constant<int, 1>{}); break;
-    case 2: go(std::integral_constant<int, 2>{}); break;
-    case 4: go(std::integral_constant<int, 4>{}); break;
-    default: go(std::integral_constant<int, 8>{}); break;
-  }
-  HDC_TRY(check_launch("reduce kernel launch"));
-  return launch_final<Acc>(partials, g, out, st);
-}
-
-
-template <class F, class S, class Acc>
-hdc_status launch_segmented(const F& f, const void* x, const int64_t* off, int64_t nseg, int64_t total, void* out,
-                            void* ws, const Tuning& t, hipStream_t st) {
-  using T = typename S::T;
-  int cus = 0;
-  HDC_TRY(compute_units(&cus));
-  const SegLayout l = seg_layout(total, nseg, t.chunk);
-  char* base = static_cast<char*>(ws);
-  SegPlan p;
-  p.cnt = reinterpret_cast<SegCounters*>(base + l.cnt);
-  p.full_list = reinterpret_cast<SegPiece*>(base + l.full);
-  p.part_list = reinterpret_cast<SegPiece*>(base + l.part);
-  p.long_base = reinterpret_cast<int32_t*>(base + l.long_base);
-  p.long_list = reinterpret_cast<int32_t*>(base + l.long_list);
-  p.partials = base + l.partials;
-  p.cap_full = l.cap_full;
-  p.cap_part = l.cap_part;
-  p.cap_partials = l.cap_partials;
-  p.chunk = t.chunk;
-  p.small_seg = t.small_seg;
-  p.spw = t.seg_per_wave;
-
-  seg_reset_kernel<<<dim3(1), dim3(64), 0, st>>>(p.cnt);
-  HDC_TRY(check_launch("segmented reset launch"));
-  seg_plan_kernel<<<dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, st>>>(off, nseg, p);
-  HDC_TRY(check_launch("segmented plan launch"));
-
-  // Persistent grid: enough wavefronts to fill the chip, never more than the
-  // largest possible item count needs.
-  const int64_t wpb = t.block / 64;
-  const int64_t max_items = l.cap_full + l.cap_part + (nseg + p.spw - 1) / p.spw;
-  int64_t g = (int64_t)cus * t.grid_mult;
-  const int64_t need = (max_items + wpb - 1) / wpb;
-  if (g > need) g = need;
-  if (g < 1) g = 1;
-  auto go = [&](auto U) {
-    constexpr int kU = decltype(U)::value;
-    seg_items_kernel<F, S, Acc, kU><<<dim3((unsigned)g), dim3(t.block), 0, st>>>(f, (const T*)x, off, nseg, p,
-                                                                                 out);
-  };
-  switch (t.unroll) {
-    case 1: go(std::integral_constant<int, 1>{}); break;
-    case 2: go(std::integral_constant<int, 2>{}); break;
-    case 4: go(std::integral_constant<int, 4>{}); break;
-    default: go(std::integral_constant<int, 8>{}); break;
-  }
-  HDC_TRY(check_launch("segmented item launch"));
-  int64_t gc = (nseg + 3) / 4;
-  if (gc > (int64_t)cus * 8) gc = (int64_t)cus * 8;
-  if (gc < 1) gc = 1;
-  seg_combine_kernel<Acc><<<dim3((unsigned)gc), dim3(256), 0, st>>>(off, nseg, p, out);
-  return check_launch("segmented combine launch");
-}
-
 }  // namespace
 
 // ===========================================================================
@@ -490,18 +259,7 @@ hdc_status hdc_map(const hdc_functor* f, hdc_dtype dt, const void* x, void* y, i
     return fail(HDC_ERR_INVALID_ARGUMENT, "x and y overlap partially");
   const Tuning t = tuning_for(HDC_OP_MAP, dt, HDC_ACC_PLAIN, n);
   hipStream_t st = (hipStream_t)stream;
-  if (dt == HDC_I32)
-    return with_int_fn(*f, [&](auto fn) { return launch_map<decltype(fn), I32>(fn, x, y, n, t, st); });
-  return with_float_storage(dt, [&](auto s) {
-    using S = decltype(s);
-    return with_float_fn(*f, [&](auto fn) -> hdc_status {
-      using F = decltype(fn);
-      if constexpr (F::binary)
-        return fail(HDC_ERR_UNSUPPORTED, "PRODUCT cannot be mapped");
-      else
-        return launch_map<F, S>(fn, x, y, n, t, st);
-    });
-  });
+  return run_map(*f, dt, x, y, n, t, st);
 }
 
 static hdc_status reduce_common(const hdc_functor* f, const hdc_functor* fm, hdc_dtype dt, const void* x,
@@ -530,38 +288,14 @@ static hdc_status reduce_common(const hdc_functor* f, const hdc_functor* fm, hdc
   HDC_TRY(resolve_workspace(workspace, ws_bytes, reduce_workspace_bytes(), st, &ws));
   const Tuning t = tuning_for(fused ? HDC_OP_MAP_REDUCE : HDC_OP_TRANSFORM_REDUCE, dt, acc, n);
 
-  if (dt == HDC_I32) {
-    return with_int_fn(*f, [&](auto fn) -> hdc_status {
-      using F = decltype(fn);
-      if (!fused) return launch_reduce<F, I32, IntAcc>(fn, x, z, n, out, ws, t, st);
-      return with_int_fn(*fm, [&](auto mfn) {
-        return launch_reduce<F, I32, IntAcc, decltype(mfn), true>(fn, x, z, n, out, ws, t, st, mfn, y);
-      });
-    });
+  if (!fused) return run_reduce(*f, dt, x, z, n, acc, out, ws, t, st);
+  switch (dt) {
+    case HDC_F32: return run_map_reduce_f32(*fm, *f, x, y, n, acc, out, ws, t, st);
+    case HDC_F16: return run_map_reduce_f16(*fm, *f, x, y, n, acc, out, ws, t, st);
+    case HDC_BF16: return run_map_reduce_bf16(*fm, *f, x, y, n, acc, out, ws, t, st);
+    case HDC_I32: return run_map_reduce_i32(*fm, *f, x, y, n, acc, out, ws, t, st);
+    default: return fail(HDC_ERR_UNSUPPORTED, "dtype %d is not provided", (int)dt);
   }
-  return with_float_storage(dt, [&](auto s) {
-    using S = decltype(s);
-    return with_float_fn(*f, [&](auto fn) -> hdc_status {
-      using F = decltype(fn);
-      auto run = [&](auto a) -> hdc_status {
-        using Acc = decltype(a);
-        if (!fused) return launch_reduce<F, S, Acc>(fn, x, z, n, out, ws, t, st);
-        if constexpr (F::binary) {
-          return fail(HDC_ERR_UNSUPPORTED, "map_reduce folds one operand");
-        } else {
-          return with_float_fn(*fm, [&](auto mfn) -> hdc_status {
-            using FM = decltype(mfn);
-            if constexpr (FM::binary)
-              return fail(HDC_ERR_UNSUPPORTED, "PRODUCT cannot be mapped");
-            else
-              return launch_reduce<F, S, Acc, FM, true>(fn, x, z, n, out, ws, t, st, mfn, y);
-          });
-        }
-      };
-      if (acc == HDC_ACC_COMPENSATED) return run(CompAcc{});
-      return run(PlainAcc{});
-    });
-  });
 }
 
 hdc_status hdc_transform_reduce(const hdc_functor* f, hdc_dtype dt, const void* x, const void* z, int64_t n,
@@ -597,23 +331,63 @@ hdc_status hdc_segmented_reduce(const hdc_functor* f, hdc_dtype dt, const void* 
   HDC_TRY(resolve_workspace(workspace, ws_bytes, seg_layout(total, num_segments, t.chunk).bytes, st, &ws));
   if ((uintptr_t)ws % 256) return fail(HDC_ERR_INVALID_ARGUMENT, "workspace is not 256-byte aligned");
 
-  if (dt == HDC_I32)
-    return with_int_fn(*f, [&](auto fn) {
-      return launch_segmented<decltype(fn), I32, IntAcc>(fn, x, offsets, num_segments, total, out, ws, t, st);
-    });
-  return with_float_storage(dt, [&](auto s) {
-    using S = decltype(s);
-    return with_float_fn(*f, [&](auto fn) -> hdc_status {
-      using F = decltype(fn);
-      if constexpr (F::binary) {
-        return fail(HDC_ERR_UNSUPPORTED, "PRODUCT is not a segmented fold term");
-      } else {
-        if (acc == HDC_ACC_COMPENSATED)
-          return launch_segmented<F, S, CompAcc>(fn, x, offsets, num_segments, total, out, ws, t, st);
-        return launch_segmented<F, S, PlainAcc>(fn, x, offsets, num_segments, total, out, ws, t, st);
-      }
-    });
-  });
+  return run_segmented(*f, dt, x, offsets, num_segments, total, acc, out, ws, t, st);
+}
+
+hdc_status hdc_batch_map_reduce(const hdc_functor* f, const hdc_functor* g, hdc_dtype dt, hdc_accum acc,
+                                const hdc_batch_call* calls, int32_t count, void* workspace, size_t ws_bytes,
+                                void* stream) {
+  if (f) HDC_TRY(check_functor(f, dt, false));
+  HDC_TRY(check_functor(g, dt, false));
+  HDC_TRY(check_acc(dt, acc));
+  if (count < 0) return fail(HDC_ERR_INVALID_ARGUMENT, "count is negative");
+  if (count == 0) return HDC_OK;
+  if (!calls) return fail(HDC_ERR_INVALID_ARGUMENT, "calls is NULL");
+  int64_t total = 0;
+  const size_t es = elem_size(dt), osz = acc == HDC_ACC_PLAIN ? 4 : 8;
+  for (int32_t i = 0; i < count; ++i) {
+    const hdc_batch_call& c = calls[i];
+    if (c.n < 0) return fail(HDC_ERR_INVALID_ARGUMENT, "call %d: n is negative", i);
+    HDC_TRY(check_ptr(c.x, dt, c.n, "x"));
+    if (!c.out || (uintptr_t)c.out % osz) return fail(HDC_ERR_INVALID_ARGUMENT, "call %d: bad out pointer", i);
+    if (f && c.y) {
+      HDC_TRY(check_ptr(c.y, dt, c.n, "y"));
+      const uintptr_t xb = (uintptr_t)c.x, yb = (uintptr_t)c.y, len = (uintptr_t)c.n * es;
+      if (c.n > 0 && xb < yb + len && yb < xb + len)
+        return fail(HDC_ERR_INVALID_ARGUMENT, "call %d: x and y overlap", i);
+    }
+    total += c.n;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const Tuning t = tuning_for(HDC_OP_BATCH, dt, acc, total / count);
+  void* ws = nullptr;
+  size_t need = batch_workspace_bytes(total, count);
+  if (need < reduce_workspace_bytes()) need = reduce_workspace_bytes();  // calls run one by one reuse it
+  HDC_TRY(resolve_workspace(workspace, ws_bytes, need, st, &ws));
+
+  // Calls whose x and y disagree in 16-byte alignment run one by one; the
+  // rest go in groups of up to kBatchMax calls.
+  int32_t grp[kBatchMax];
+  int ng = 0;
+  char* wsb = static_cast<char*>(ws);  // groups run in stream order and share it
+  auto flush = [&]() -> hdc_status {
+    if (ng == 0) return HDC_OK;
+    const hdc_status r = run_batch(f, *g, dt, acc, calls, grp, ng, wsb, t, st);
+    ng = 0;
+    return r;
+  };
+  for (int32_t i = 0; i < count; ++i) {
+    const hdc_batch_call& c = calls[i];
+    const bool vec = !(f && c.y) || ((uintptr_t)c.x % 16) == ((uintptr_t)c.y % 16);
+    if (!vec) {
+      if (f && c.y)
+        HDC_TRY(hdc_map_reduce(f, g, dt, c.x, c.y, c.n, acc, c.out, ws, need, stream));
+      continue;
+    }
+    grp[ng++] = i;
+    if (ng == kBatchMax) HDC_TRY(flush());
+  }
+  return flush();
 }
 
 hdc_status hdc_workspace_size(int op, hdc_dtype dt, hdc_accum acc, int64_t n, int64_t num_segments,
@@ -626,6 +400,10 @@ hdc_status hdc_workspace_size(int op, hdc_dtype dt, hdc_accum acc, int64_t n, in
     case HDC_OP_MAP: *bytes = 0; return HDC_OK;
     case HDC_OP_TRANSFORM_REDUCE:
     case HDC_OP_MAP_REDUCE: *bytes = reduce_workspace_bytes(); return HDC_OK;
+    case HDC_OP_BATCH:
+      *bytes = batch_workspace_bytes(n, num_segments);
+      if (*bytes < reduce_workspace_bytes()) *bytes = reduce_workspace_bytes();  // calls run one by one reuse it
+      return HDC_OK;
     case HDC_OP_SEGMENTED_REDUCE:
       if (n / kMinChunk >= INT32_MAX / 2 || num_segments >= INT32_MAX)
         return fail(HDC_ERR_INVALID_ARGUMENT, "sizes too large");

@@ -1,0 +1,175 @@
+// Host-side helpers shared by the translation units of the library: error
+// reporting, tuning records, launch geometry, the functor-id -> type and
+// dtype -> storage dispatch, and the per-family launchers (each family is
+// compiled in its own translation unit so the build runs in parallel).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstddef>
+
+#include "hdc.h"
+#include "hdc_functors.hpp"
+#include "hdc_kernels.hpp"
+#include "hdc_segmented.hpp"
+
+namespace hdc {
+
+// Record a failure for hdc_last_error() and return `s`.
+hdc_status fail(hdc_status s, const char* fmt, ...);
+// Compute units of the current device (cached per device).
+hdc_status compute_units(int* cus);
+
+inline hdc_status check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(HDC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+  return HDC_OK;
+}
+
+struct Tuning {
+  int block = 256;
+  int unroll = 4;
+  int grid_mult = 8;
+  int chunk = 4096;
+  int small_seg = 128;
+  int seg_per_wave = 8;
+};
+
+
+#define HDC_TRY(expr)                 \
+  do {                                \
+    hdc_status s_ = (expr);           \
+    if (s_ != HDC_OK) return s_;      \
+  } while (0)
+
+
+constexpr int64_t kMaxGrid = 65536;  // upper bound on pass-1 blocks
+constexpr size_t kPartialBytes = 8;  // every fold state fits 8 bytes
+
+inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+inline size_t reduce_workspace_bytes() { return round_up(kMaxGrid * kPartialBytes, 256); }
+
+constexpr int64_t kMinChunk = 1024;
+
+// Layout of the segmented workspace for a given chunk (sections 256-byte aligned).
+struct SegLayout {
+  size_t cnt, full, part, long_base, long_list, partials, bytes;
+  int64_t cap_full, cap_part, cap_partials;
+};
+
+// Partial slots of a grouped batch: at most total/chunk + count chunks.
+inline size_t batch_workspace_bytes(int64_t total, int64_t count) {
+  return round_up((size_t)(total / kMinChunk + count + 1) * kPartialBytes, 256);
+}
+
+inline SegLayout seg_layout(int64_t total, int64_t S, int64_t chunk) {
+  SegLayout l{};
+  l.cap_full = total / chunk + 1;
+  l.cap_part = S > 0 ? S : 1;
+  l.cap_partials = l.cap_full + l.cap_part;
+  size_t o = 0;
+  l.cnt = o;       o += round_up(sizeof(SegCounters), 256);
+  l.full = o;      o += round_up((size_t)l.cap_full * sizeof(SegPiece), 256);
+  l.part = o;      o += round_up((size_t)l.cap_part * sizeof(SegPiece), 256);
+  l.long_base = o; o += round_up((size_t)l.cap_part * sizeof(int32_t), 256);
+  l.long_list = o; o += round_up((size_t)l.cap_part * sizeof(int32_t), 256);
+  l.partials = o;  o += round_up((size_t)l.cap_partials * kPartialBytes, 256);
+  l.bytes = o;
+  return l;
+}
+
+
+template <class Body>
+hdc_status with_float_fn(const hdc_functor& f, Body&& body) {
+  switch (f.id) {
+    case HDC_FN_IDENTITY: return body(Identity{});
+    case HDC_FN_AFFINE: return body(Affine{f.a, f.b});
+    case HDC_FN_HORNER: {
+      Horner h{};
+      h.degree = f.degree;
+      for (int k = 0; k <= f.degree; ++k) h.c[k] = f.coef[k];
+      return body(h);
+    }
+    case HDC_FN_PRODUCT: return body(Product{});
+  }
+  return fail(HDC_ERR_INVALID_ARGUMENT, "unknown functor id %d", f.id);
+}
+
+template <class Body>
+hdc_status with_int_fn(const hdc_functor& f, Body&& body) {
+  switch (f.id) {
+    case HDC_FN_IDENTITY: return body(IntIdentity{});
+    case HDC_FN_AFFINE: return body(IntAffine{f.ia, f.ib});
+  }
+  return fail(HDC_ERR_UNSUPPORTED, "functor %d is not provided for int32", f.id);
+}
+
+template <class Body>
+hdc_status with_float_storage(hdc_dtype dt, Body&& body) {
+  switch (dt) {
+    case HDC_F32: return body(F32{});
+    case HDC_F16: return body(F16{});
+    case HDC_BF16: return body(BF16{});
+    default: return fail(HDC_ERR_UNSUPPORTED, "dtype %d is not floating-point storage", (int)dt);
+  }
+}
+
+
+template <class S>
+inline Range make_range(const void* x, int64_t n, bool vector) {
+  Range r{n, 0, 0, 0, 0};
+  if (!vector) return r;
+  const int64_t es = sizeof(typename S::T);
+  const int64_t mis = (int64_t)((uintptr_t)x % 16);
+  int64_t head = mis ? (16 - mis) / es : 0;
+  if (head > n) head = n;
+  r.head = head;
+  r.nvec = (n - head) / S::kVec;
+  r.tail_start = head + r.nvec * S::kVec;
+  r.tail = n - r.tail_start;
+  return r;
+}
+
+inline int64_t grid_for(int64_t units, int64_t per_block, int cus, const Tuning& t) {
+  int64_t g = (units + per_block - 1) / per_block;
+  int64_t cap = (int64_t)cus * t.grid_mult;
+  if (cap > kMaxGrid) cap = kMaxGrid;
+  if (g > cap) g = cap;
+  if (g < 1) g = 1;
+  return g;
+}
+
+
+// Chunk length (in 16-byte vectors) of a grouped batch: the tuning's element
+// count, at least one block step and a whole number of block steps.
+inline int64_t batch_chunk_vecs(const Tuning& t, int kvec) {
+  const int64_t step = (int64_t)t.block * t.unroll;
+  int64_t v = t.chunk / kvec;
+  if (v < step) v = step;
+  return v / step * step;
+}
+
+
+// Per-family launchers (one translation unit each).
+hdc_status run_map(const hdc_functor& f, hdc_dtype dt, const void* x, void* y, int64_t n, const Tuning& t,
+                   hipStream_t st);
+hdc_status run_reduce(const hdc_functor& f, hdc_dtype dt, const void* x, const void* z, int64_t n, hdc_accum acc,
+                      void* out, void* ws, const Tuning& t, hipStream_t st);
+// Fused map + reduce, one translation unit per storage type.
+hdc_status run_map_reduce_f32(const hdc_functor& fm, const hdc_functor& f, const void* x, void* y, int64_t n,
+                              hdc_accum acc, void* out, void* ws, const Tuning& t, hipStream_t st);
+hdc_status run_map_reduce_f16(const hdc_functor& fm, const hdc_functor& f, const void* x, void* y, int64_t n,
+                              hdc_accum acc, void* out, void* ws, const Tuning& t, hipStream_t st);
+hdc_status run_map_reduce_bf16(const hdc_functor& fm, const hdc_functor& f, const void* x, void* y, int64_t n,
+                               hdc_accum acc, void* out, void* ws, const Tuning& t, hipStream_t st);
+hdc_status run_map_reduce_i32(const hdc_functor& fm, const hdc_functor& f, const void* x, void* y, int64_t n,
+                              hdc_accum acc, void* out, void* ws, const Tuning& t, hipStream_t st);
+hdc_status run_segmented(const hdc_functor& f, hdc_dtype dt, const void* x, const int64_t* off, int64_t nseg,
+                         int64_t total, hdc_accum acc, void* out, void* ws, const Tuning& t, hipStream_t st);
+hdc_status run_batch(const hdc_functor* fm, const hdc_functor& g, hdc_dtype dt, hdc_accum acc,
+                     const hdc_batch_call* calls, const int32_t* idx, int cnt, void* ws, const Tuning& t,
+                     hipStream_t st);
+
+}  // namespace hdc

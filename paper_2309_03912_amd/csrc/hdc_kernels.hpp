@@ -117,27 +117,40 @@ __global__ __launch_bounds__(1024) void map_kernel(F f, const elem_t<S>* x, elem
     const elem_t<S>* xv = x + r.head;
     elem_t<S>* yv = y + r.head;
     const int64_t nchunk = (r.nvec + B * U - 1) / (B * U);
-    for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
-      const int64_t base = c * B * U + tid;
-      const bool full = c * B * U + B * U <= r.nvec;
-      elem_t<S> in[U * S::kVec], out[U * S::kVec];
+    // Full chunks take the unguarded branch, so all U loads of a lane are
+    // issued back to back; only the last chunk checks bounds per vector.
+    auto step = [&](int64_t base, auto full_c) {
+      constexpr bool kFull = decltype(full_c)::value;
+      Vec<S> a[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        Vec<S> v{};
-        if (full || base + u * B < r.nvec) v = load16<S>(xv + (base + u * B) * S::kVec);
-#pragma unroll
-        for (int k = 0; k < S::kVec; ++k) in[u * S::kVec + k] = v.e[k];
+        if (kFull || base + u * B < r.nvec)
+          a[u] = load16<S>(xv + (base + u * B) * S::kVec);
+        else
+          a[u] = Vec<S>{};
       }
+      elem_t<S> in[U * S::kVec], out[U * S::kVec];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int k = 0; k < S::kVec; ++k) in[u * S::kVec + k] = a[u].e[k];
       map_batch<F, S>(f, in, out);
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        if (full || base + u * B < r.nvec) {
+        if (kFull || base + u * B < r.nvec) {
           Vec<S> o;
 #pragma unroll
           for (int k = 0; k < S::kVec; ++k) o.e[k] = out[u * S::kVec + k];
           store16_nt<S>(yv + (base + u * B) * S::kVec, o);
         }
       }
+    };
+    for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
+      const int64_t base = c * B * U + tid;
+      if (c * B * U + B * U <= r.nvec)
+        step(base, std::true_type{});
+      else
+        step(base, std::false_type{});
     }
     // Unaligned head and tail: the last block's first threads.
     if (blockIdx.x == gridDim.x - 1) {
@@ -203,30 +216,35 @@ __global__ __launch_bounds__(1024) void reduce_kernel(F f, const elem_t<S>* x, c
     const elem_t<S>* xv = x + r.head;
     const elem_t<S>* zv = F::binary ? z + r.head : nullptr;
     const int64_t nchunk = (r.nvec + B * U - 1) / (B * U);
-    for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
-      const int64_t base = c * B * U + tid;
-      const bool full = c * B * U + B * U <= r.nvec;
+    auto step = [&](int64_t base, auto full_c) {
+      constexpr bool kFull = decltype(full_c)::value;
+      Vec<S> a[U], b[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (kFull || base + u * B < r.nvec) {
+          a[u] = load16<S>(xv + (base + u * B) * S::kVec);
+          if constexpr (F::binary) b[u] = load16<S>(zv + (base + u * B) * S::kVec);
+        } else {
+          a[u] = Vec<S>{};
+          b[u] = Vec<S>{};
+        }
+      }
       elem_t<S> v[N], w[N];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        Vec<S> a{}, b{};
-        if (full || base + u * B < r.nvec) {
-          a = load16<S>(xv + (base + u * B) * S::kVec);
-          if constexpr (F::binary) b = load16<S>(zv + (base + u * B) * S::kVec);
-        }
 #pragma unroll
         for (int k = 0; k < S::kVec; ++k) {
-          v[u * S::kVec + k] = a.e[k];
-          w[u * S::kVec + k] = b.e[k];
+          v[u * S::kVec + k] = a[u].e[k];
+          w[u * S::kVec + k] = F::binary ? b[u].e[k] : a[u].e[k];
         }
       }
-      fold_step(v, w, [&](int i) { return full || base + (i / S::kVec) * B < r.nvec; });
+      fold_step(v, w, [&](int i) { return kFull || base + (i / S::kVec) * B < r.nvec; });
       if constexpr (kMap) {
         elem_t<S> o[N];
         map_batch<FM, S>(fm, v, o);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          if (full || base + u * B < r.nvec) {
+          if (kFull || base + u * B < r.nvec) {
             Vec<S> ov;
 #pragma unroll
             for (int k = 0; k < S::kVec; ++k) ov.e[k] = o[u * S::kVec + k];
@@ -234,6 +252,13 @@ __global__ __launch_bounds__(1024) void reduce_kernel(F f, const elem_t<S>* x, c
           }
         }
       }
+    };
+    for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
+      const int64_t base = c * B * U + tid;
+      if (c * B * U + B * U <= r.nvec)
+        step(base, std::true_type{});
+      else
+        step(base, std::false_type{});
     }
     if (blockIdx.x == gridDim.x - 1) {
       if (tid < r.head) {

@@ -1,0 +1,173 @@
+// Launch templates of the kernel families: grid geometry and kernel-instance
+// choice (unroll) for one concrete (callable, storage, fold) combination.
+#pragma once
+
+#include <type_traits>
+
+#include "hdc_batch.hpp"
+#include "hdc_host.hpp"
+
+namespace hdc {
+
+template <class F, class S>
+hdc_status launch_map(const F& f, const void* x, void* y, int64_t n, const Tuning& t, hipStream_t st) {
+  using T = typename S::T;
+  int cus = 0;
+  HDC_TRY(compute_units(&cus));
+  const bool vec = ((uintptr_t)x % 16) == ((uintptr_t)y % 16);
+  Range r = make_range<S>(x, n, vec);
+  const int64_t units = vec ? r.nvec : n;
+  const int64_t g = grid_for(units, (int64_t)t.block * t.unroll, cus, t);
+  auto go = [&](auto U) {
+    constexpr int kU = decltype(U)::value;
+    if (vec)
+      map_kernel<F, S, kU, true><<<dim3((unsigned)g), dim3(t.block), 0, st>>>(f, (const T*)x, (T*)y, r);
+    else
+      map_kernel<F, S, kU, false><<<dim3((unsigned)g), dim3(t.block), 0, st>>>(f, (const T*)x, (T*)y, r);
+  };
+  switch (t.unroll) {
+    case 1: go(std::integral_constant<int, 1>{}); break;
+    case 2: go(std::integral_constant<int, 2>{}); break;
+    case 4: go(std::integral_constant<int, 4>{}); break;
+    default: go(std::integral_constant<int, 8>{}); break;
+  }
+  return check_launch("map kernel launch");
+}
+
+template <class Acc>
+hdc_status launch_final(const Acc* partials, int64_t g, void* out, hipStream_t st) {
+  reduce_final_kernel<Acc><<<dim3(1), dim3(256), 0, st>>>(partials, (int)g, out);
+  return check_launch("final combine launch");
+}
+
+template <class F, class S, class Acc, class FM = Identity, bool kMap = false>
+hdc_status launch_reduce(const F& f, const void* x, const void* z, int64_t n, void* out, void* ws,
+                         const Tuning& t, hipStream_t st, const FM& fm = FM{}, void* y = nullptr) {
+  using T = typename S::T;
+  int cus = 0;
+  HDC_TRY(compute_units(&cus));
+  bool vec = true;
+  if (F::binary && ((uintptr_t)x % 16) != ((uintptr_t)z % 16)) vec = false;
+  if (kMap && ((uintptr_t)x % 16) != ((uintptr_t)y % 16)) vec = false;
+  Range r = make_range<S>(x, n, vec);
+  const int64_t units = vec ? r.nvec : n;
+  const int64_t g = grid_for(units, (int64_t)t.block * t.unroll, cus, t);
+  Acc* partials = static_cast<Acc*>(ws);
+  auto go = [&](auto U) {
+    constexpr int kU = decltype(U)::value;
+    if (vec)
+      reduce_kernel<F, S, Acc, kU, true, FM, kMap><<<dim3((unsigned)g), dim3(t.block), 0, st>>>(
+          f, (const T*)x, (const T*)z, r, partials, fm, (T*)y);
+    else
+      reduce_kernel<F, S, Acc, kU, false, FM, kMap><<<dim3((unsigned)g), dim3(t.block), 0, st>>>(
+          f, (const T*)x, (const T*)z, r, partials, fm, (T*)y);
+  };
+  switch (t.unroll) {
+    case 1: go(std::integral_constant<int, 1>{}); break;
+    case 2: go(std::integral_constant<int, 2>{}); break;
+    case 4: go(std::integral_constant<int, 4>{}); break;
+    default: go(std::integral_constant<int, 8>{}); break;
+  }
+  HDC_TRY(check_launch("reduce kernel launch"));
+  return launch_final<Acc>(partials, g, out, st);
+}
+
+
+template <class F, class S, class Acc>
+hdc_status launch_segmented(const F& f, const void* x, const int64_t* off, int64_t nseg, int64_t total, void* out,
+                            void* ws, const Tuning& t, hipStream_t st) {
+  using T = typename S::T;
+  int cus = 0;
+  HDC_TRY(compute_units(&cus));
+  const SegLayout l = seg_layout(total, nseg, t.chunk);
+  char* base = static_cast<char*>(ws);
+  SegPlan p;
+  p.cnt = reinterpret_cast<SegCounters*>(base + l.cnt);
+  p.full_list = reinterpret_cast<SegPiece*>(base + l.full);
+  p.part_list = reinterpret_cast<SegPiece*>(base + l.part);
+  p.long_base = reinterpret_cast<int32_t*>(base + l.long_base);
+  p.long_list = reinterpret_cast<int32_t*>(base + l.long_list);
+  p.partials = base + l.partials;
+  p.cap_full = l.cap_full;
+  p.cap_part = l.cap_part;
+  p.cap_partials = l.cap_partials;
+  p.chunk = t.chunk;
+  p.small_seg = t.small_seg;
+  p.spw = t.seg_per_wave;
+
+  seg_reset_kernel<<<dim3(1), dim3(64), 0, st>>>(p.cnt);
+  HDC_TRY(check_launch("segmented reset launch"));
+  seg_plan_kernel<<<dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, st>>>(off, nseg, p);
+  HDC_TRY(check_launch("segmented plan launch"));
+
+  // Persistent grid: enough wavefronts to fill the chip, never more than the
+  // largest possible item count needs.
+  const int64_t wpb = t.block / 64;
+  const int64_t max_items = l.cap_full + l.cap_part + (nseg + p.spw - 1) / p.spw;
+  int64_t g = (int64_t)cus * t.grid_mult;
+  const int64_t need = (max_items + wpb - 1) / wpb;
+  if (g > need) g = need;
+  if (g < 1) g = 1;
+  auto go = [&](auto U) {
+    constexpr int kU = decltype(U)::value;
+    seg_items_kernel<F, S, Acc, kU><<<dim3((unsigned)g), dim3(t.block), 0, st>>>(f, (const T*)x, off, nseg, p,
+                                                                                 out);
+  };
+  switch (t.unroll) {
+    case 1: go(std::integral_constant<int, 1>{}); break;
+    case 2: go(std::integral_constant<int, 2>{}); break;
+    case 4: go(std::integral_constant<int, 4>{}); break;
+    default: go(std::integral_constant<int, 8>{}); break;
+  }
+  HDC_TRY(check_launch("segmented item launch"));
+  int64_t gc = (nseg + 3) / 4;
+  if (gc > (int64_t)cus * 8) gc = (int64_t)cus * 8;
+  if (gc < 1) gc = 1;
+  seg_combine_kernel<Acc><<<dim3((unsigned)gc), dim3(256), 0, st>>>(off, nseg, p, out);
+  return check_launch("segmented combine launch");
+}
+
+template <class FM, class F, class S, class Acc>
+hdc_status launch_batch(const FM& fm, const F& f, const hdc_batch_call* calls, const int32_t* idx, int cnt,
+                        void* ws, const Tuning& t, hipStream_t st) {
+  int cus = 0;
+  HDC_TRY(compute_units(&cus));
+  BatchTable tab{};
+  tab.count = cnt;
+  tab.chunk_vecs = batch_chunk_vecs(t, S::kVec);
+  int64_t acc_chunks = 0;
+  for (int q = 0; q < cnt; ++q) {
+    const hdc_batch_call& c = calls[idx[q]];
+    BatchCall& b = tab.call[q];
+    b.x = c.x;
+    b.y = c.y;
+    b.out = c.out;
+    b.r = make_range<S>(c.x, c.n, true);
+    tab.prefix[q] = acc_chunks;
+    if (c.n > 0) {
+      int64_t nc = (b.r.nvec + tab.chunk_vecs - 1) / tab.chunk_vecs;
+      acc_chunks += nc > 0 ? nc : 1;
+    }
+  }
+  tab.prefix[cnt] = acc_chunks;
+  Acc* partials = static_cast<Acc*>(ws);
+  if (acc_chunks > 0) {
+    int64_t g = (int64_t)cus * t.grid_mult;
+    if (g > acc_chunks) g = acc_chunks;
+    auto go = [&](auto U) {
+      constexpr int kU = decltype(U)::value;
+      batch_kernel<FM, F, S, Acc, kU><<<dim3((unsigned)g), dim3(t.block), 0, st>>>(fm, f, tab, partials);
+    };
+    switch (t.unroll) {
+      case 1: go(std::integral_constant<int, 1>{}); break;
+      case 2: go(std::integral_constant<int, 2>{}); break;
+      case 4: go(std::integral_constant<int, 4>{}); break;
+      default: go(std::integral_constant<int, 8>{}); break;
+    }
+    HDC_TRY(check_launch("batch launch"));
+  }
+  batch_combine_kernel<Acc><<<dim3((unsigned)((cnt + 3) / 4)), dim3(256), 0, st>>>(tab, partials);
+  return check_launch("batch combine launch");
+}
+
+}  // namespace hdc

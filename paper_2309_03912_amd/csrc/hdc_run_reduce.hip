@@ -1,0 +1,20 @@
+// Launcher of the transform_reduce / dot family (own translation unit).
+#include "hdc_launch.hpp"
+
+namespace hdc {
+
+hdc_status run_reduce(const hdc_functor& f, hdc_dtype dt, const void* x, const void* z, int64_t n, hdc_accum acc,
+                      void* out, void* ws, const Tuning& t, hipStream_t st) {
+  if (dt == HDC_I32)
+    return with_int_fn(f, [&](auto fn) { return launch_reduce<decltype(fn), I32, IntAcc>(fn, x, z, n, out, ws, t, st); });
+  return with_float_storage(dt, [&](auto s) {
+    using S = decltype(s);
+    return with_float_fn(f, [&](auto fn) -> hdc_status {
+      using F = decltype(fn);
+      if (acc == HDC_ACC_COMPENSATED) return launch_reduce<F, S, CompAcc>(fn, x, z, n, out, ws, t, st);
+      return launch_reduce<F, S, PlainAcc>(fn, x, z, n, out, ws, t, st);
+    });
+  });
+}
+
+}  // namespace hdc

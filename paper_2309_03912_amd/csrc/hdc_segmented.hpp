@@ -53,7 +53,7 @@ struct SegPlan {
   int32_t spw;           // small segments per wavefront (power of two, <= 64)
 };
 
-__global__ void seg_reset_kernel(SegCounters* c) {
+static __global__ void seg_reset_kernel(SegCounters* c) {
   if (threadIdx.x == 0) *c = SegCounters{0, 0, 0, 0};
 }
 
@@ -81,7 +81,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* l
 }
 
 // One thread per segment.
-__global__ __launch_bounds__(256) void seg_plan_kernel(const int64_t* __restrict__ off, int64_t S, SegPlan p) {
+static __global__ __launch_bounds__(256) void seg_plan_kernel(const int64_t* __restrict__ off, int64_t S, SegPlan p) {
   __shared__ uint32_t lds[kMaxWaves];
   __shared__ uint32_t bases[4];
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -154,17 +154,24 @@ __device__ __forceinline__ Acc wave_fold_range(const F& f, const elem_t<S>* __re
   if (lane < head) fold_elem<F, S>(acc[0], f, x[s + lane], x[s + lane]);
   if (lane < e - t0) fold_elem<F, S>(acc[1 % KV], f, x[t0 + lane], x[t0 + lane]);
   const elem_t<S>* xv = x + b0;
-  for (int64_t v0 = 0; v0 < nvec; v0 += 64 * U) {
-    elem_t<S> v[N];
+  // Full strides take the unguarded branch (all U loads in flight at once).
+  auto step = [&](int64_t v0, auto full_c) {
+    constexpr bool kFull = decltype(full_c)::value;
+    Vec<S> a[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t vi = v0 + u * 64 + lane;
-      Vec<S> a{};
-      if (vi < nvec) a = load16<S>(xv + vi * KV);
-#pragma unroll
-      for (int k = 0; k < KV; ++k) v[u * KV + k] = a.e[k];
+      if (kFull || vi < nvec)
+        a[u] = load16<S>(xv + vi * KV);
+      else
+        a[u] = Vec<S>{};
     }
-    auto ok = [&](int i) { return v0 + (i / KV) * 64 + lane < nvec; };
+    elem_t<S> v[N];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < KV; ++k) v[u * KV + k] = a[u].e[k];
+    auto ok = [&](int i) { return kFull || v0 + (i / KV) * 64 + lane < nvec; };
     if constexpr (!kInt) {
       float t[N];
 #pragma unroll
@@ -178,7 +185,10 @@ __device__ __forceinline__ Acc wave_fold_range(const F& f, const elem_t<S>* __re
       for (int i = 0; i < N; ++i)
         if (ok(i)) fold_elem<F, S>(acc[i % KV], f, v[i], v[i]);
     }
-  }
+  };
+  int64_t v0 = 0;
+  for (; v0 + 64 * U <= nvec; v0 += 64 * U) step(v0, std::true_type{});
+  if (v0 < nvec) step(v0, std::false_type{});
   Acc t = acc[0];
 #pragma unroll
   for (int k = 1; k < KV; ++k) t = Acc::merge(t, acc[k]);
