@@ -178,6 +178,23 @@ hdc_status hdc_batch_map_reduce(const hdc_functor* f, const hdc_functor* g,
                                 void* workspace, size_t ws_bytes,
                                 void* stream);
 
+/*
+ * The host side of the same callables (the paper's one-callable-two-sides
+ * idea, section 2.10 and appendix B): x, y, z and out are HOST pointers, the
+ * call is synchronous and runs on `nthreads` host threads (0: all hardware
+ * threads).  Element semantics are those of hdc_map / hdc_transform_reduce
+ * (the same C++ code evaluates them); reductions fold contiguous per-thread
+ * ranges and merge them in thread order, so their last bits depend on
+ * nthreads.  These are separate entry points: the device entry points never
+ * run on the host.
+ */
+hdc_status hdc_host_map(const hdc_functor* f, hdc_dtype dt, const void* x,
+                        void* y, int64_t n, int32_t nthreads);
+hdc_status hdc_host_transform_reduce(const hdc_functor* f, hdc_dtype dt,
+                                     const void* x, const void* z, int64_t n,
+                                     hdc_accum acc, void* out,
+                                     int32_t nthreads);
+
 /* Bytes of workspace `op` needs for these sizes (0 for HDC_OP_MAP).  For
  * HDC_OP_SEGMENTED_REDUCE, n is `total` and num_segments is S; for
  * HDC_OP_BATCH, n is the sum of the calls' n and num_segments the count. */

@@ -40,6 +40,7 @@ FN = {"identity": FN_IDENTITY, "affine": FN_AFFINE, "horner": FN_HORNER, "produc
 # Every symbol include/hdc.h declares.
 EXPORTS = [
     "hdc_map", "hdc_transform_reduce", "hdc_segmented_reduce", "hdc_map_reduce", "hdc_batch_map_reduce",
+    "hdc_host_map", "hdc_host_transform_reduce",
     "hdc_workspace_size", "hdc_validate_offsets", "hdc_set_tuning", "hdc_get_tuning",
     "hdc_load_tuning", "hdc_tuning_bucket", "hdc_status_string", "hdc_last_error", "hdc_version",
 ]
@@ -90,6 +91,8 @@ def lib() -> ctypes.CDLL:
         L.hdc_map_reduce.argtypes = [P(Functor), P(Functor), i32, vp, vp, i64, i32, vp, vp, ctypes.c_size_t, vp]
         L.hdc_batch_map_reduce.argtypes = [P(Functor), P(Functor), i32, i32, P(BatchCall), ctypes.c_int32, vp,
                                            ctypes.c_size_t, vp]
+        L.hdc_host_map.argtypes = [P(Functor), i32, vp, vp, i64, ctypes.c_int32]
+        L.hdc_host_transform_reduce.argtypes = [P(Functor), i32, vp, vp, i64, i32, vp, ctypes.c_int32]
         L.hdc_workspace_size.argtypes = [i32, i32, i32, i64, i64, P(ctypes.c_size_t)]
         L.hdc_validate_offsets.argtypes = [vp, i64, i64, vp]
         L.hdc_set_tuning.argtypes = [i32, i32, i32, i32, P(Tuning)]
@@ -97,7 +100,7 @@ def lib() -> ctypes.CDLL:
         L.hdc_tuning_bucket.argtypes = [i64, P(ctypes.c_int32)]
         L.hdc_load_tuning.argtypes = [ctypes.c_char_p]
         for name in ["hdc_map", "hdc_transform_reduce", "hdc_segmented_reduce", "hdc_map_reduce",
-                     "hdc_batch_map_reduce",
+                     "hdc_batch_map_reduce", "hdc_host_map", "hdc_host_transform_reduce",
                      "hdc_workspace_size", "hdc_validate_offsets", "hdc_set_tuning", "hdc_get_tuning",
                      "hdc_load_tuning", "hdc_tuning_bucket"]:
             getattr(L, name).restype = st
@@ -311,6 +314,36 @@ def batch_map_reduce(xs, map_fn, reduce_fn, acc="plain", ys=None, outs=None, ws=
     _check(lib().hdc_batch_map_reduce(f, ctypes.byref(g), dt, a, table, len(xs), ws.data_ptr(), ws.numel(),
                                       _stream(xs[0])))
     return ys, outs
+
+
+def _host_tensor(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.device.type != "cpu":
+        raise ValueError(f"{name} must be a CPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def host_map(x: torch.Tensor, fn, out: torch.Tensor | None = None, threads: int = 0) -> torch.Tensor:
+    """The host side of map: the same callables on CPU tensors (synchronous)."""
+    x = _host_tensor(x, "x")
+    y = torch.empty_like(x) if out is None else _host_tensor(out, "out")
+    f = make_functor(fn)
+    _check(lib().hdc_host_map(ctypes.byref(f), _dtype(x), x.data_ptr(), y.data_ptr(), x.numel(), threads))
+    return y
+
+
+def host_transform_reduce(x: torch.Tensor, fn, acc="plain", z: torch.Tensor | None = None,
+                          threads: int = 0) -> torch.Tensor:
+    """The host side of transform_reduce on CPU tensors (synchronous); 0-d CPU tensor."""
+    x = _host_tensor(x, "x")
+    a = _acc(acc)
+    zp = _host_tensor(z, "z").data_ptr() if z is not None else None
+    r = torch.empty((), dtype=OUT_DTYPE[a])
+    f = make_functor(fn)
+    _check(lib().hdc_host_transform_reduce(ctypes.byref(f), _dtype(x), x.data_ptr(), zp, x.numel(), a,
+                                           r.data_ptr(), threads))
+    return r
 
 
 def validate_offsets(offsets: torch.Tensor, total: int) -> None:

@@ -390,6 +390,35 @@ hdc_status hdc_batch_map_reduce(const hdc_functor* f, const hdc_functor* g, hdc_
   return flush();
 }
 
+
+hdc_status hdc_host_map(const hdc_functor* f, hdc_dtype dt, const void* x, void* y, int64_t n, int32_t nthreads) {
+  HDC_TRY(check_functor(f, dt, false));
+  if (n < 0) return fail(HDC_ERR_INVALID_ARGUMENT, "n = %lld is negative", (long long)n);
+  if (nthreads < 0) return fail(HDC_ERR_INVALID_ARGUMENT, "nthreads is negative");
+  HDC_TRY(check_ptr(x, dt, n, "x"));
+  HDC_TRY(check_ptr(y, dt, n, "y"));
+  if (n == 0) return HDC_OK;
+  const uintptr_t xb = (uintptr_t)x, yb = (uintptr_t)y, len = (uintptr_t)n * elem_size(dt);
+  if (xb != yb && xb < yb + len && yb < xb + len)
+    return fail(HDC_ERR_INVALID_ARGUMENT, "x and y overlap partially");
+  return run_host_map(*f, dt, x, y, n, nthreads);
+}
+
+hdc_status hdc_host_transform_reduce(const hdc_functor* f, hdc_dtype dt, const void* x, const void* z, int64_t n,
+                                     hdc_accum acc, void* out, int32_t nthreads) {
+  HDC_TRY(check_functor(f, dt, true));
+  HDC_TRY(check_acc(dt, acc));
+  if (n < 0) return fail(HDC_ERR_INVALID_ARGUMENT, "n = %lld is negative", (long long)n);
+  if (nthreads < 0) return fail(HDC_ERR_INVALID_ARGUMENT, "nthreads is negative");
+  HDC_TRY(check_ptr(x, dt, n, "x"));
+  if (f->id == HDC_FN_PRODUCT) {
+    if (!z && n > 0) return fail(HDC_ERR_UNSUPPORTED, "PRODUCT needs the second operand z");
+    HDC_TRY(check_ptr(z, dt, n, "z"));
+  }
+  if (!out) return fail(HDC_ERR_INVALID_ARGUMENT, "out is NULL");
+  return run_host_reduce(*f, dt, x, z, n, acc, out, nthreads);
+}
+
 hdc_status hdc_workspace_size(int op, hdc_dtype dt, hdc_accum acc, int64_t n, int64_t num_segments,
                               size_t* bytes) {
   if (!bytes) return fail(HDC_ERR_INVALID_ARGUMENT, "bytes is NULL");

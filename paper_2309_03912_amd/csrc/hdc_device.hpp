@@ -40,7 +40,7 @@ __device__ __forceinline__ void store16_nt(typename S::T* p, const Vec<S>& v) {
 // ---------------------------------------------------------------------------
 
 // s = fl(a + b) and e with a + b = s + e exactly (no branch, 6 flops).
-__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+__host__ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
   s = a + b;
   float bp = s - a;
   float ap = s - bp;
@@ -54,30 +54,30 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
 
 struct PlainAcc {
   float s;
-  __device__ static PlainAcc zero() { return {0.0f}; }
-  __device__ void add(float t) { s += t; }
-  __device__ void add_product(float x, float z) { s = __builtin_fmaf(x, z, s); }
-  __device__ static PlainAcc merge(PlainAcc a, PlainAcc b) { return {a.s + b.s}; }
+  __host__ __device__ static PlainAcc zero() { return {0.0f}; }
+  __host__ __device__ void add(float t) { s += t; }
+  __host__ __device__ void add_product(float x, float z) { s = __builtin_fmaf(x, z, s); }
+  __host__ __device__ static PlainAcc merge(PlainAcc a, PlainAcc b) { return {a.s + b.s}; }
 };
 
 // Sum in fp32 with the rounding error of every addition captured by TwoSum
 // and accumulated separately (compensated / doubled-precision summation).
 struct CompAcc {
   float s, c;
-  __device__ static CompAcc zero() { return {0.0f, 0.0f}; }
-  __device__ void add(float t) {
+  __host__ __device__ static CompAcc zero() { return {0.0f, 0.0f}; }
+  __host__ __device__ void add(float t) {
     float e;
     two_sum(s, t, s, e);
     c += e;
   }
   // x*z = p + q exactly (fma computes the rounding error of the product).
   template <bool kExactProduct>
-  __device__ void add_product(float x, float z) {
+  __host__ __device__ void add_product(float x, float z) {
     float p = x * z;
     add(p);
     if constexpr (!kExactProduct) c += __builtin_fmaf(x, z, -p);
   }
-  __device__ static CompAcc merge(CompAcc a, CompAcc b) {
+  __host__ __device__ static CompAcc merge(CompAcc a, CompAcc b) {
     CompAcc r;
     float e;
     two_sum(a.s, b.s, r.s, e);
@@ -89,9 +89,9 @@ struct CompAcc {
 // int64 sum, wrapping mod 2^64.
 struct IntAcc {
   uint64_t s;
-  __device__ static IntAcc zero() { return {0}; }
-  __device__ void add(uint64_t t) { s += t; }
-  __device__ static IntAcc merge(IntAcc a, IntAcc b) { return {a.s + b.s}; }
+  __host__ __device__ static IntAcc zero() { return {0}; }
+  __host__ __device__ void add(uint64_t t) { s += t; }
+  __host__ __device__ static IntAcc merge(IntAcc a, IntAcc b) { return {a.s + b.s}; }
 };
 
 // ---------------------------------------------------------------------------

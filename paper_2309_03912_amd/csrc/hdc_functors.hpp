@@ -117,22 +117,22 @@ struct IntAffine {
 struct F32 {
   using T = float;
   static constexpr int kVec = 4;
-  __device__ static float widen(T v) { return v; }
-  __device__ static T narrow(float v) { return v; }
+  __host__ __device__ static float widen(T v) { return v; }
+  __host__ __device__ static T narrow(float v) { return v; }
 };
 
 struct F16 {
   using T = _Float16;
   static constexpr int kVec = 8;
-  __device__ static float widen(T v) { return (float)v; }       // exact
-  __device__ static T narrow(float v) { return (_Float16)v; }   // RNE
+  __host__ __device__ static float widen(T v) { return (float)v; }       // exact
+  __host__ __device__ static T narrow(float v) { return (_Float16)v; }   // RNE
 };
 
 struct BF16 {
   using T = __bf16;
   static constexpr int kVec = 8;
-  __device__ static float widen(T v) { return (float)v; }       // exact
-  __device__ static T narrow(float v) { return (__bf16)v; }     // RNE
+  __host__ __device__ static float widen(T v) { return (float)v; }       // exact
+  __host__ __device__ static T narrow(float v) { return (__bf16)v; }     // RNE
 };
 
 struct I32 {

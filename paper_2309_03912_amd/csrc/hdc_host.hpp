@@ -172,4 +172,9 @@ hdc_status run_batch(const hdc_functor* fm, const hdc_functor& g, hdc_dtype dt, 
                      const hdc_batch_call* calls, const int32_t* idx, int cnt, void* ws, const Tuning& t,
                      hipStream_t st);
 
+// The host side (hdc_host_map / hdc_host_transform_reduce).
+hdc_status run_host_map(const hdc_functor& f, hdc_dtype dt, const void* x, void* y, int64_t n, int32_t nthreads);
+hdc_status run_host_reduce(const hdc_functor& f, hdc_dtype dt, const void* x, const void* z, int64_t n,
+                           hdc_accum acc, void* out, int32_t nthreads);
+
 }  // namespace hdc

@@ -1,0 +1,103 @@
+// The host side of the same callables.  The paper's subject is one generic
+// callable usable from host and device code, with the execution space taken
+// from the callable's type (section 2.10, "SFINAE 3 with macro"; the trait of
+// appendix B).  These templates run the HstDev callables of the library on
+// host memory through the very element semantics the kernels use (map_elem,
+// fold_elem and the fold states are __host__ __device__); they are
+// constrained to host_callable types, so a device-only callable is a compile
+// error here exactly as a host-only one is in a kernel.
+#pragma once
+
+#include <cstdint>
+#include <thread>
+#include <vector>
+
+#include "hdc_host.hpp"
+
+namespace hdc {
+
+template <class F, class S>
+  requires host_callable<F>
+void host_map_range(const F& f, const elem_t<S>* x, elem_t<S>* y, int64_t lo, int64_t hi) {
+  for (int64_t i = lo; i < hi; ++i) y[i] = map_elem<F, S>(f, x[i]);
+}
+
+// Blocked fold of [lo, hi): blocks of kHostBlock elements into four
+// interleaved states, block totals merged in order -- short plain-fp32 chains
+// whatever the range length.
+constexpr int64_t kHostBlock = 4096;
+
+template <class F, class S, class Acc>
+  requires host_callable<F>
+Acc host_fold_range(const F& f, const elem_t<S>* x, const elem_t<S>* z, int64_t lo, int64_t hi) {
+  Acc total = Acc::zero();
+  for (int64_t b = lo; b < hi; b += kHostBlock) {
+    const int64_t e = hi < b + kHostBlock ? hi : b + kHostBlock;
+    Acc part[4] = {Acc::zero(), Acc::zero(), Acc::zero(), Acc::zero()};
+    for (int64_t i = b; i < e; ++i) fold_elem<F, S>(part[(i - b) & 3], f, x[i], F::binary ? z[i] : x[i]);
+    total = Acc::merge(total, Acc::merge(Acc::merge(part[0], part[1]), Acc::merge(part[2], part[3])));
+  }
+  return total;
+}
+
+// Split [0, n) into `parts` contiguous ranges; part p is [lo(p), lo(p+1)).
+inline int64_t host_part_lo(int64_t n, int parts, int p) { return n / parts * p + (p < n % parts ? p : n % parts); }
+
+inline int host_threads(int32_t requested, int64_t n) {
+  int t = requested > 0 ? requested : (int)std::thread::hardware_concurrency();
+  if (t < 1) t = 1;
+  const int64_t min_per_thread = 1 << 16;
+  if ((int64_t)t > (n + min_per_thread - 1) / min_per_thread) t = (int)((n + min_per_thread - 1) / min_per_thread);
+  return t < 1 ? 1 : t;
+}
+
+template <class Fn>
+void host_parallel(int parts, Fn&& fn) {
+  if (parts == 1) {
+    fn(0);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(parts);
+  for (int p = 0; p < parts; ++p) th.emplace_back([&fn, p] { fn(p); });
+  for (auto& t : th) t.join();
+}
+
+template <class F, class S>
+  requires host_callable<F>
+void host_map(const F& f, const void* x, void* y, int64_t n, int32_t nthreads) {
+  using T = elem_t<S>;
+  const int parts = host_threads(nthreads, n);
+  host_parallel(parts, [&](int p) {
+    host_map_range<F, S>(f, (const T*)x, (T*)y, host_part_lo(n, parts, p), host_part_lo(n, parts, p + 1));
+  });
+}
+
+// Each thread folds its contiguous range; the thread states are merged in
+// thread order (plain: fp32; compensated: fp64 of s + c; integers: wrapping).
+template <class F, class S, class Acc>
+  requires host_callable<F>
+void host_reduce(const F& f, const void* x, const void* z, int64_t n, void* out, int32_t nthreads) {
+  using T = elem_t<S>;
+  const int parts = host_threads(nthreads, n);
+  std::vector<Acc> st(parts);
+  host_parallel(parts, [&](int p) {
+    st[p] = host_fold_range<F, S, Acc>(f, (const T*)x, (const T*)z, host_part_lo(n, parts, p),
+                                       host_part_lo(n, parts, p + 1));
+  });
+  if constexpr (std::is_same_v<Acc, PlainAcc>) {
+    float s = 0.0f;
+    for (const Acc& a : st) s += a.s;
+    *static_cast<float*>(out) = s;
+  } else if constexpr (std::is_same_v<Acc, CompAcc>) {
+    double s = 0.0;
+    for (const Acc& a : st) s += __builtin_isfinite(a.s) ? (double)a.s + (double)a.c : (double)a.s;
+    *static_cast<double*>(out) = s;
+  } else {
+    uint64_t s = 0;
+    for (const Acc& a : st) s += a.s;
+    *static_cast<int64_t*>(out) = (int64_t)s;
+  }
+}
+
+}  // namespace hdc

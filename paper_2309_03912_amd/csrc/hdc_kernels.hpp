@@ -35,7 +35,7 @@ using elem_t = typename S::T;
 // ---------------------------------------------------------------------------
 
 template <class F, class S>
-__device__ __forceinline__ elem_t<S> map_elem(const F& f, elem_t<S> x) {
+__host__ __device__ __forceinline__ elem_t<S> map_elem(const F& f, elem_t<S> x) {
   if constexpr (std::is_same_v<S, I32>)
     return f.map(x);
   else if constexpr (std::is_same_v<F, Identity>)
@@ -45,7 +45,7 @@ __device__ __forceinline__ elem_t<S> map_elem(const F& f, elem_t<S> x) {
 }
 
 template <class F, class S, class Acc>
-__device__ __forceinline__ void fold_elem(Acc& a, const F& f, elem_t<S> x, elem_t<S> z) {
+__host__ __device__ __forceinline__ void fold_elem(Acc& a, const F& f, elem_t<S> x, elem_t<S> z) {
   if constexpr (std::is_same_v<S, I32>) {
     a.add(f.term(x));
   } else if constexpr (F::binary) {
@@ -63,7 +63,7 @@ __device__ __forceinline__ void fold_elem(Acc& a, const F& f, elem_t<S> x, elem_
 // value) feeds N independent fma chains; each element still sees exactly the
 // fma sequence of Horner::operator(), so results are bit-identical to it.
 template <class F, int N>
-__device__ __forceinline__ void eval_batch(const F& f, float (&t)[N]) {
+__host__ __device__ __forceinline__ void eval_batch(const F& f, float (&t)[N]) {
   if constexpr (std::is_same_v<F, Horner>) {
     float acc[N];
     const float top = f.c[f.degree];
@@ -191,9 +191,25 @@ __global__ __launch_bounds__(1024) void reduce_kernel(F f, const elem_t<S>* x, c
   constexpr bool kBatch = !kInt && !F::binary;  // unary float callables run as one batch
   constexpr int K = kVector ? S::kVec : U;
   constexpr int N = kVector ? U * S::kVec : U;  // elements per lane per step
-  Acc acc[K];
+  // Two-level fold: `acc` takes the terms of at most kFlush steps, then is
+  // merged into `outer`.  A plain fp32 chain then never grows longer than
+  // kFlush * U terms plus one term per kFlush steps, whatever the grid size,
+  // which keeps its rounding error far below the tolerance.
+  constexpr int kFlush = 8;
+  Acc acc[K], outer[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) acc[k] = Acc::zero();
+  for (int k = 0; k < K; ++k) acc[k] = outer[k] = Acc::zero();
+  int since_flush = 0;
+  auto maybe_flush = [&]() {
+    if (++since_flush == kFlush) {
+      since_flush = 0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        outer[k] = Acc::merge(outer[k], acc[k]);
+        acc[k] = Acc::zero();
+      }
+    }
+  };
 
   // Fold N loaded elements; `ok(i)` tells whether element slot i is real.
   auto fold_step = [&](const elem_t<S>(&v)[N], const elem_t<S>(&w)[N], auto ok) {
@@ -259,6 +275,7 @@ __global__ __launch_bounds__(1024) void reduce_kernel(F f, const elem_t<S>* x, c
         step(base, std::true_type{});
       else
         step(base, std::false_type{});
+      if constexpr (std::is_same_v<Acc, PlainAcc>) maybe_flush();
     }
     if (blockIdx.x == gridDim.x - 1) {
       if (tid < r.head) {
@@ -283,6 +300,7 @@ __global__ __launch_bounds__(1024) void reduce_kernel(F f, const elem_t<S>* x, c
         else w[u] = v[u];
       }
       fold_step(v, w, [&](int u) { return i + u * stride < r.n; });
+      if constexpr (std::is_same_v<Acc, PlainAcc>) maybe_flush();
       if constexpr (kMap) {
         elem_t<S> o[N];
         map_batch<FM, S>(fm, v, o);
@@ -293,9 +311,11 @@ __global__ __launch_bounds__(1024) void reduce_kernel(F f, const elem_t<S>* x, c
     }
   }
 
-  Acc t = acc[0];
 #pragma unroll
-  for (int k = 1; k < K; ++k) t = Acc::merge(t, acc[k]);
+  for (int k = 0; k < K; ++k) outer[k] = Acc::merge(outer[k], acc[k]);
+  Acc t = outer[0];
+#pragma unroll
+  for (int k = 1; k < K; ++k) t = Acc::merge(t, outer[k]);
   t = block_reduce(t, MergeOp<Acc>{}, lds);
   if (tid == 0) partials[blockIdx.x] = t;
 }

@@ -24,3 +24,18 @@ static_assert(hdc::hdc_of<hdc::Horner> == hdc::HDC::HstDev);
 void launch(const float* x, float* y, hdc::Range r) {
   hdc::map_kernel<Callable, hdc::F32, 1, true><<<1, 64>>>(Callable{}, x, y, r);
 }
+
+#ifdef PROBE_HOST_SIDE
+#include "hdc_host_side.hpp"
+struct DevOnly {  // device-only callable: the host side must reject it
+  static constexpr hdc::HDC hdc = hdc::HDC::Dev;
+  static constexpr bool binary = false;
+  __device__ float operator()(float x) const { return x; }
+};
+#ifdef PROBE_HOST_DEVONLY
+using HostCallable = DevOnly;
+#else
+using HostCallable = hdc::Horner;
+#endif
+void host_probe(const float* x, float* y) { hdc::host_map<HostCallable, hdc::F32>(HostCallable{}, x, y, 4, 1); }
+#endif

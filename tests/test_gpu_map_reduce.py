@@ -260,3 +260,19 @@ def test_map_reduce_fused(dt):
             assert r.item() == ref["isum"]
         else:
             assert_close_sum(r.item(), ref, f"fused {dt} n={n}")
+
+
+def test_smallest_grid_on_large_input_stays_within_tolerance():
+    # one 64-thread block per compute unit, one vector per step: each lane
+    # folds ~1000 terms, which a single fp32 chain would not keep within 1e-6
+    n = 1 << 26
+    x = synth.uniform_pm1_f32(33, 0, n)
+    ref = oracle.reduce(FNS["horner"], x)
+    g = x.to(gpu())
+    b = hdc.tuning_bucket(n)
+    old = hdc.get_tuning(hdc.OP_TRANSFORM_REDUCE, hdc.F32, hdc.ACC_PLAIN, b)
+    try:
+        hdc.set_tuning(hdc.OP_TRANSFORM_REDUCE, hdc.F32, hdc.ACC_PLAIN, b, block=64, unroll=1, grid_mult=1)
+        assert_close_sum(hdc.transform_reduce(g, FNS["horner"]).item(), ref, "smallest grid")
+    finally:
+        hdc.set_tuning(hdc.OP_TRANSFORM_REDUCE, hdc.F32, hdc.ACC_PLAIN, b, **old)
