@@ -76,8 +76,13 @@ typedef enum hdc_accum {
   HDC_ACC_PLAIN = 0,       /* floats: fp32 partial sums; `out` is one float */
   HDC_ACC_COMPENSATED = 1, /* floats: fp32 TwoSum-compensated partials, fp64
                               final cross-block combine; `out` is one double */
-  HDC_ACC_EXACT_INT = 2    /* int32: int64 sums wrapping mod 2^64; `out` is
+  HDC_ACC_EXACT_INT = 2,   /* int32: int64 sums wrapping mod 2^64; `out` is
                               one int64 */
+  HDC_ACC_EXACT = 3        /* fp16 storage, IDENTITY fold: the exact real sum
+                              rounded once to fp64 (nearest-even); `out` is
+                              one double.  Independent of order and tuning:
+                              bit-reproducible.  transform_reduce and
+                              map_reduce only. */
 } hdc_accum;
 
 typedef enum hdc_op {

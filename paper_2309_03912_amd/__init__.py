@@ -28,13 +28,14 @@ TUNING_CACHE = os.path.join(HERE, "tuning_gfx950.txt")
 OK, ERR_INVALID_ARGUMENT, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP = range(5)
 F32, F16, BF16, I32, I64, F64 = range(6)
 FN_IDENTITY, FN_AFFINE, FN_HORNER, FN_PRODUCT = range(4)
-ACC_PLAIN, ACC_COMPENSATED, ACC_EXACT_INT = range(3)
+ACC_PLAIN, ACC_COMPENSATED, ACC_EXACT_INT, ACC_EXACT = range(4)
 OP_MAP, OP_TRANSFORM_REDUCE, OP_SEGMENTED_REDUCE, OP_MAP_REDUCE, OP_BATCH = range(5)
 MAX_DEGREE = 16
 
 DTYPE = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16, torch.int32: I32}
-ACC = {"plain": ACC_PLAIN, "compensated": ACC_COMPENSATED, "exact_int": ACC_EXACT_INT}
-OUT_DTYPE = {ACC_PLAIN: torch.float32, ACC_COMPENSATED: torch.float64, ACC_EXACT_INT: torch.int64}
+ACC = {"plain": ACC_PLAIN, "compensated": ACC_COMPENSATED, "exact_int": ACC_EXACT_INT, "exact": ACC_EXACT}
+OUT_DTYPE = {ACC_PLAIN: torch.float32, ACC_COMPENSATED: torch.float64, ACC_EXACT_INT: torch.int64,
+             ACC_EXACT: torch.float64}
 FN = {"identity": FN_IDENTITY, "affine": FN_AFFINE, "horner": FN_HORNER, "product": FN_PRODUCT}
 
 # Every symbol include/hdc.h declares.

@@ -71,7 +71,7 @@ namespace {
 // Tuning
 // ---------------------------------------------------------------------------
 
-constexpr int kOps = 5, kDtypes = 6, kAccs = 3, kBuckets = 4;
+constexpr int kOps = 5, kDtypes = 6, kAccs = 4, kBuckets = 4;
 std::mutex g_tune_mu;
 Tuning g_tune[kOps][kDtypes][kAccs][kBuckets];
 
@@ -224,8 +224,9 @@ hdc_status check_functor(const hdc_functor* f, hdc_dtype dt, bool allow_product)
 }
 
 hdc_status check_acc(hdc_dtype dt, hdc_accum acc) {
-  if (acc != HDC_ACC_PLAIN && acc != HDC_ACC_COMPENSATED && acc != HDC_ACC_EXACT_INT)
+  if (acc != HDC_ACC_PLAIN && acc != HDC_ACC_COMPENSATED && acc != HDC_ACC_EXACT_INT && acc != HDC_ACC_EXACT)
     return fail(HDC_ERR_INVALID_ARGUMENT, "unknown accumulation %d", (int)acc);
+  if (acc == HDC_ACC_EXACT && dt != HDC_F16) return fail(HDC_ERR_UNSUPPORTED, "EXACT needs fp16 storage");
   if (is_float(dt) && acc == HDC_ACC_EXACT_INT)
     return fail(HDC_ERR_UNSUPPORTED, "EXACT_INT needs int32 storage");
   if (dt == HDC_I32 && acc != HDC_ACC_EXACT_INT)
@@ -269,6 +270,8 @@ static hdc_status reduce_common(const hdc_functor* f, const hdc_functor* fm, hdc
   HDC_TRY(check_functor(f, dt, !fused));
   if (fused) HDC_TRY(check_functor(fm, dt, false));
   HDC_TRY(check_acc(dt, acc));
+  if (acc == HDC_ACC_EXACT && f->id != HDC_FN_IDENTITY)
+    return fail(HDC_ERR_UNSUPPORTED, "EXACT folds the IDENTITY callable only");
   if (n < 0) return fail(HDC_ERR_INVALID_ARGUMENT, "n = %lld is negative", (long long)n);
   HDC_TRY(check_ptr(x, dt, n, "x"));
   if (f->id == HDC_FN_PRODUCT) {
@@ -314,6 +317,7 @@ hdc_status hdc_segmented_reduce(const hdc_functor* f, hdc_dtype dt, const void* 
                                 size_t ws_bytes, void* stream) {
   HDC_TRY(check_functor(f, dt, false));
   HDC_TRY(check_acc(dt, acc));
+  if (acc == HDC_ACC_EXACT) return fail(HDC_ERR_UNSUPPORTED, "EXACT is provided for transform_reduce and map_reduce");
   if (num_segments < 0) return fail(HDC_ERR_INVALID_ARGUMENT, "num_segments is negative");
   if (num_segments >= INT32_MAX) return fail(HDC_ERR_INVALID_ARGUMENT, "more than 2^31 - 2 segments");
   if (total < 0) return fail(HDC_ERR_INVALID_ARGUMENT, "total is negative");
@@ -340,6 +344,7 @@ hdc_status hdc_batch_map_reduce(const hdc_functor* f, const hdc_functor* g, hdc_
   if (f) HDC_TRY(check_functor(f, dt, false));
   HDC_TRY(check_functor(g, dt, false));
   HDC_TRY(check_acc(dt, acc));
+  if (acc == HDC_ACC_EXACT) return fail(HDC_ERR_UNSUPPORTED, "EXACT is provided for transform_reduce and map_reduce");
   if (count < 0) return fail(HDC_ERR_INVALID_ARGUMENT, "count is negative");
   if (count == 0) return HDC_OK;
   if (!calls) return fail(HDC_ERR_INVALID_ARGUMENT, "calls is NULL");
@@ -408,6 +413,7 @@ hdc_status hdc_host_transform_reduce(const hdc_functor* f, hdc_dtype dt, const v
                                      hdc_accum acc, void* out, int32_t nthreads) {
   HDC_TRY(check_functor(f, dt, true));
   HDC_TRY(check_acc(dt, acc));
+  if (acc == HDC_ACC_EXACT) return fail(HDC_ERR_UNSUPPORTED, "EXACT is provided on the device only");
   if (n < 0) return fail(HDC_ERR_INVALID_ARGUMENT, "n = %lld is negative", (long long)n);
   if (nthreads < 0) return fail(HDC_ERR_INVALID_ARGUMENT, "nthreads is negative");
   HDC_TRY(check_ptr(x, dt, n, "x"));

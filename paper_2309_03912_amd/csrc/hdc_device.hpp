@@ -94,6 +94,77 @@ struct IntAcc {
   __host__ __device__ static IntAcc merge(IntAcc a, IntAcc b) { return {a.s + b.s}; }
 };
 
+// Exact sum of fp16 values.  Every fp16 value is an integer multiple of 2^-24
+// below 2^16 in magnitude, so a chain of at most 2^13 of them summed in fp64
+// never rounds (each partial sum is a multiple of 2^-24 below 2^29: 53 bits).
+// `d` is such a chain; `normalize` moves it, exactly, into a 128-bit
+// two's-complement integer in units of 2^-24 (lo, hi).  Infinities and NaNs
+// are kept apart in `nf`, whose IEEE sum is the result whenever it is not 0.
+// Callers keep every fp64 chain at most 2^13 terms long.
+struct ExactAcc {
+  double d;
+  float nf;
+  uint32_t pad;
+  uint64_t lo;
+  uint64_t hi;
+  __host__ __device__ static ExactAcc zero() { return {0.0, 0.0f, 0u, 0u, 0u}; }
+  __host__ __device__ void add(float t) { d += (double)t; }
+  __host__ __device__ void normalize() {
+    if (!__builtin_isfinite(d)) {
+      nf += (float)d;
+    } else if (d != 0.0) {
+      const int64_t q = (int64_t)(d * 16777216.0);  // exact: an integer below 2^53
+      const uint64_t l = lo + (uint64_t)q;
+      hi += (uint64_t)(q >> 63) + (l < lo ? 1u : 0u);
+      lo = l;
+    }
+    d = 0.0;
+  }
+  __host__ __device__ static ExactAcc merge(ExactAcc a, ExactAcc b) {
+    a.normalize();
+    b.normalize();
+    ExactAcc r;
+    r.d = 0.0;
+    r.nf = a.nf + b.nf;
+    r.pad = 0;
+    r.lo = a.lo + b.lo;
+    r.hi = a.hi + b.hi + (r.lo < a.lo ? 1u : 0u);
+    return r;
+  }
+  // The exact total rounded once to fp64 (nearest, ties to even).
+  __host__ __device__ double value() const {
+    ExactAcc t = *this;
+    t.normalize();
+    if (t.nf != 0.0f || t.nf != t.nf) return (double)t.nf;
+    const bool neg = (int64_t)t.hi < 0;
+    uint64_t ml = t.lo, mh = t.hi;
+    if (neg) {  // magnitude of the two's complement
+      ml = ~ml + 1;
+      mh = ~mh + (ml == 0 ? 1u : 0u);
+    }
+    int top = -1;  // index of the highest set bit of the 128-bit magnitude
+    if (mh) top = 127 - __builtin_clzll(mh);
+    else if (ml) top = 63 - __builtin_clzll(ml);
+    if (top < 0) return 0.0;
+    double r;
+    if (top < 53) {
+      r = (double)ml;  // exact
+    } else {
+      const int sh = top - 52;  // drop the `sh` low bits, keep 53
+      auto bit = [&](int i) -> uint64_t { return i >= 64 ? (mh >> (i - 64)) & 1u : (ml >> i) & 1u; };
+      uint64_t m = 0;
+      for (int i = top; i >= sh; --i) m = (m << 1) | bit(i);
+      const uint64_t guard = bit(sh - 1);
+      uint64_t sticky = 0;
+      for (int i = sh - 2; i >= 0 && !sticky; --i) sticky = bit(i);
+      if (guard && (sticky || (m & 1u))) m += 1;
+      r = __builtin_ldexp((double)m, sh);  // m <= 2^53: exact
+    }
+    r = __builtin_ldexp(r, -24);
+    return neg ? -r : r;
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Wavefront reduction with DPP lane moves (wave64).
 // ---------------------------------------------------------------------------

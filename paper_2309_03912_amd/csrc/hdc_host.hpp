@@ -45,7 +45,7 @@ struct Tuning {
 
 
 constexpr int64_t kMaxGrid = 65536;  // upper bound on pass-1 blocks
-constexpr size_t kPartialBytes = 8;  // every fold state fits 8 bytes
+constexpr size_t kPartialBytes = 32;  // every fold state fits 32 bytes
 
 inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 

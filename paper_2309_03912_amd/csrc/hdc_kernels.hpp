@@ -275,7 +275,7 @@ __global__ __launch_bounds__(1024) void reduce_kernel(F f, const elem_t<S>* x, c
         step(base, std::true_type{});
       else
         step(base, std::false_type{});
-      if constexpr (std::is_same_v<Acc, PlainAcc>) maybe_flush();
+      if constexpr (std::is_same_v<Acc, PlainAcc> || std::is_same_v<Acc, ExactAcc>) maybe_flush();
     }
     if (blockIdx.x == gridDim.x - 1) {
       if (tid < r.head) {
@@ -300,7 +300,7 @@ __global__ __launch_bounds__(1024) void reduce_kernel(F f, const elem_t<S>* x, c
         else w[u] = v[u];
       }
       fold_step(v, w, [&](int u) { return i + u * stride < r.n; });
-      if constexpr (std::is_same_v<Acc, PlainAcc>) maybe_flush();
+      if constexpr (std::is_same_v<Acc, PlainAcc> || std::is_same_v<Acc, ExactAcc>) maybe_flush();
       if constexpr (kMap) {
         elem_t<S> o[N];
         map_batch<FM, S>(fm, v, o);
@@ -325,6 +325,7 @@ __global__ __launch_bounds__(1024) void reduce_kernel(F f, const elem_t<S>* x, c
 // (thread-strided, then the fixed block reduction) and writes the result.
 //   PlainAcc -> float (fp32 sum); CompAcc -> double (fp64 sum of s + c, or of
 //   s alone when s is not finite: TwoSum of an infinity yields NaN in c);
+//   ExactAcc -> double (the exact 128-bit total rounded once);
 //   IntAcc -> int64 (wrapping).
 // ---------------------------------------------------------------------------
 
@@ -350,6 +351,12 @@ __global__ __launch_bounds__(256) void reduce_final_kernel(const Acc* partials, 
     }
     s = block_reduce(s, AddF64{}, lds);
     if (tid == 0) *static_cast<double*>(out) = s;
+  } else if constexpr (std::is_same_v<Acc, ExactAcc>) {
+    __shared__ ExactAcc lds[kMaxWaves];
+    ExactAcc s = ExactAcc::zero();
+    for (int i = tid; i < G; i += blockDim.x) s = ExactAcc::merge(s, partials[i]);
+    s = block_reduce(s, MergeOp<ExactAcc>{}, lds);
+    if (tid == 0) *static_cast<double*>(out) = s.value();
   } else {
     __shared__ uint64_t lds[kMaxWaves];
     uint64_t s = 0;

@@ -22,6 +22,17 @@ hdc_status HDC_MR_NAME(const hdc_functor& fm, const hdc_functor& f, const void* 
       });
     });
   } else {
+    if constexpr (std::is_same_v<S, F16>) {
+      if (acc == HDC_ACC_EXACT)  // checked on entry: the fold callable is IDENTITY
+        return with_float_fn(fm, [&](auto mfn) -> hdc_status {
+          using FM = decltype(mfn);
+          if constexpr (FM::binary)
+            return fail(HDC_ERR_UNSUPPORTED, "PRODUCT cannot be mapped");
+          else
+            return launch_reduce<Identity, F16, ExactAcc, FM, true>(Identity{}, x, nullptr, n, out, ws, t, st, mfn,
+                                                                   y);
+        });
+    }
     return with_float_fn(f, [&](auto fn) -> hdc_status {
       using F = decltype(fn);
       if constexpr (F::binary) {

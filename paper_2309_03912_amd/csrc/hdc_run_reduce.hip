@@ -7,6 +7,9 @@ hdc_status run_reduce(const hdc_functor& f, hdc_dtype dt, const void* x, const v
                       void* out, void* ws, const Tuning& t, hipStream_t st) {
   if (dt == HDC_I32)
     return with_int_fn(f, [&](auto fn) { return launch_reduce<decltype(fn), I32, IntAcc>(fn, x, z, n, out, ws, t, st); });
+  if (acc == HDC_ACC_EXACT) {  // checked on entry: IDENTITY on F16 storage
+    return launch_reduce<Identity, F16, ExactAcc>(Identity{}, x, z, n, out, ws, t, st);
+  }
   return with_float_storage(dt, [&](auto s) {
     using S = decltype(s);
     return with_float_fn(f, [&](auto fn) -> hdc_status {

@@ -276,3 +276,51 @@ def test_smallest_grid_on_large_input_stays_within_tolerance():
         assert_close_sum(hdc.transform_reduce(g, FNS["horner"]).item(), ref, "smallest grid")
     finally:
         hdc.set_tuning(hdc.OP_TRANSFORM_REDUCE, hdc.F32, hdc.ACC_PLAIN, b, **old)
+
+
+# --------------------------------------------------------------------------
+# exact fp16 sums: bit-exact against the oracle, whatever the tuning
+# --------------------------------------------------------------------------
+
+def _fp16_cases():
+    yield "uniform", synth.to_storage(synth.uniform_pm1_f32(51, 0, (1 << 20) + 5).double(), torch.float16)
+    yield "wide", synth.to_storage(synth.normal_f64(52, 0, 300007) * torch.exp(
+        3.0 * synth.normal_f64(52, 1, 300007)), torch.float16)  # subnormals to 65504
+    v, _ = synth.ill_conditioned(synth.seed_of(3), 1 << 20, torch.float16)
+    yield "kappa1e8", v
+    yield "tiny", torch.tensor([2.0 ** -24, -2.0 ** -24, 2.0 ** -24, 65504.0, -65504.0, 1.0], dtype=torch.float16)
+    for n in (0, 1, 7, 8, 9, 4097):
+        yield f"n{n}", synth.to_storage(synth.uniform_pm1_f32(n + 60, 0, n).double() * 1000, torch.float16)
+
+
+def test_exact_fp16_sum_is_bit_exact():
+    for name, x in _fp16_cases():
+        r = hdc.transform_reduce(x.to(gpu()), {"fn": "identity"}, "exact").item()
+        assert r == oracle.reduce({"fn": "identity"}, x)["exact"], name
+
+
+def test_exact_fp16_sum_independent_of_tuning():
+    x = synth.to_storage(synth.normal_f64(53, 0, (1 << 22) + 3) * 100, torch.float16)
+    ref = oracle.reduce({"fn": "identity"}, x)["exact"]
+    g = x.to(gpu())
+    b = hdc.tuning_bucket(x.numel())
+    old = hdc.get_tuning(hdc.OP_TRANSFORM_REDUCE, hdc.F16, hdc.ACC_EXACT, b)
+    try:
+        for block, unroll, gm in [(64, 1, 1), (256, 4, 8), (1024, 8, 64), (128, 2, 3)]:
+            hdc.set_tuning(hdc.OP_TRANSFORM_REDUCE, hdc.F16, hdc.ACC_EXACT, b, block=block, unroll=unroll,
+                           grid_mult=gm)
+            assert hdc.transform_reduce(g, {"fn": "identity"}, "exact").item() == ref, (block, unroll, gm)
+    finally:
+        hdc.set_tuning(hdc.OP_TRANSFORM_REDUCE, hdc.F16, hdc.ACC_EXACT, b, **old)
+
+
+def test_exact_fp16_nonfinite_and_fused():
+    x = torch.zeros(10000, dtype=torch.float16)
+    x[5] = math.inf
+    assert hdc.transform_reduce(x.to(gpu()), {"fn": "identity"}, "exact").item() == math.inf
+    x[9000] = -math.inf
+    assert math.isnan(hdc.transform_reduce(x.to(gpu()), {"fn": "identity"}, "exact").item())
+    x = synth.to_storage(synth.uniform_pm1_f32(54, 0, 100003).double(), torch.float16)
+    y, r = hdc.map_reduce(x.to(gpu()), FNS["affine"], {"fn": "identity"}, "exact")
+    assert torch.equal(bits(y.cpu()), bits(oracle.map(FNS["affine"], x)))
+    assert r.item() == oracle.reduce({"fn": "identity"}, x)["exact"]
