@@ -117,7 +117,7 @@ def test_map_reduce_and_segmented_reject_bad_arguments():
 def test_workspace_sizes():
     assert hdc.workspace_size(hdc.OP_MAP, hdc.F32, 0, 1 << 20) == 0
     a = hdc.workspace_size(hdc.OP_TRANSFORM_REDUCE, hdc.F32, 0, 1 << 28)
-    assert 0 < a <= 1 << 20
+    assert 0 < a <= 1 << 22
     with pytest.raises(hdc.HdcError):
         hdc.workspace_size(99, hdc.F32, 0, 10)
     with pytest.raises(hdc.HdcError):
