@@ -90,7 +90,8 @@ typedef enum hdc_op {
   HDC_OP_TRANSFORM_REDUCE = 1,
   HDC_OP_SEGMENTED_REDUCE = 2,
   HDC_OP_MAP_REDUCE = 3,
-  HDC_OP_BATCH = 4
+  HDC_OP_BATCH = 4,
+  HDC_OP_SCAN = 5
 } hdc_op;
 
 #define HDC_MAX_DEGREE 16
@@ -156,6 +157,20 @@ hdc_status hdc_map_reduce(const hdc_functor* f, const hdc_functor* g,
                           hdc_dtype dt, const void* x, void* y, int64_t n,
                           hdc_accum acc, void* out, void* workspace,
                           size_t ws_bytes, void* stream);
+
+/*
+ * Prefix sums: y[i] = the fold of f over x[0..i] (exclusive = 1: over
+ * x[0..i-1], so y[0] = 0).  acc PLAIN (y: float), COMPENSATED (y: double)
+ * for F32/F16/BF16, EXACT_INT (y: int64, wrapping) for I32; IDENTITY,
+ * AFFINE, HORNER.  Three stream-ordered passes (tile sums, tile offsets,
+ * tile scans) with no waiting between blocks; results are bit-reproducible
+ * for a fixed tuning.  x and y must not overlap.  Workspace:
+ * hdc_workspace_size(HDC_OP_SCAN, dt, acc, n, 0, ...).  Bytes moved: x is
+ * read twice, y written once.
+ */
+hdc_status hdc_scan(const hdc_functor* f, hdc_dtype dt, const void* x,
+                    void* y, int64_t n, hdc_accum acc, int32_t exclusive,
+                    void* workspace, size_t ws_bytes, void* stream);
 
 /* One call of a grouped batch (device pointers). */
 typedef struct hdc_batch_call {

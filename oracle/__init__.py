@@ -83,6 +83,9 @@ def lib():
         L.or_segmented.restype = ctypes.c_int
         L.or_segmented.argtypes = [P(OrFn), ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_int64, P(OrResult)]
+        L.or_scan.restype = ctypes.c_int
+        L.or_scan.argtypes = [P(OrFn), ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.or_exact_sum.restype = ctypes.c_double
         L.or_exact_sum.argtypes = [ctypes.c_void_p, ctypes.c_int64]
         _lib = L
@@ -156,6 +159,25 @@ def segmented(spec: dict, x: torch.Tensor, offsets: torch.Tensor) -> dict:
         "isum": np.array([res[j].isum for j in range(S)], dtype=np.int64),
     }
     return out
+
+
+def scan(spec: dict, x: torch.Tensor, exclusive: bool = False) -> dict:
+    """Prefix sums of f(x) (numpy arrays): exact / abs_sum for floats, isum for int32."""
+    x = _host(x)
+    n = x.numel()
+    f = make_fn(spec)
+    if x.dtype == torch.int32:
+        out = np.zeros(n, dtype=np.int64)
+        if lib().or_scan(ctypes.byref(f), DTYPES[x.dtype], x.data_ptr(), n, int(exclusive), None, None,
+                         out.ctypes.data) != 0:
+            raise ValueError("oracle: unsupported scan")
+        return {"isum": out}
+    ex = np.zeros(n)
+    ab = np.zeros(n)
+    if lib().or_scan(ctypes.byref(f), DTYPES[x.dtype], x.data_ptr(), n, int(exclusive), ex.ctypes.data,
+                     ab.ctypes.data, None) != 0:
+        raise ValueError("oracle: unsupported scan")
+    return {"exact": ex, "abs_sum": ab}
 
 
 def exact_sum(v) -> float:

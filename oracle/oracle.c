@@ -202,8 +202,25 @@ static void sa_add(sacc *s, double v) {
   if (++s->since_norm >= SA_RENORM) sa_carry(s);
 }
 
-static int sa_bit(const int64_t *d, int i) {
-  return (int)((d[i / 32] >> (i % 32)) & 1);
+/* Bits [pos, pos + cnt) of the non-negative digit array (cnt <= 53,
+ * pos >= 0), read as an integer. */
+static uint64_t sa_bits(const int64_t *d, int pos, int cnt) {
+  int w = pos / 32, sh = pos % 32;
+  unsigned __int128 v = 0;
+  for (int k = 2; k >= 0; --k) {
+    v <<= 32;
+    if (w + k < SA_DIGITS) v |= (uint32_t)d[w + k];
+  }
+  return (uint64_t)(v >> sh) & ((cnt == 64 ? 0 : ((uint64_t)1 << cnt)) - 1);
+}
+
+/* Whether any bit below position pos (exclusive) is set. */
+static int sa_any_below(const int64_t *d, int pos) {
+  if (pos <= 0) return 0;
+  int w = pos / 32, sh = pos % 32;
+  for (int k = 0; k < w; ++k)
+    if (d[k]) return 1;
+  return sh && ((uint32_t)d[w] & (((uint32_t)1 << sh) - 1)) != 0;
 }
 
 static double sa_round(sacc *s) {
@@ -223,23 +240,20 @@ static double sa_round(sacc *s) {
     }
   }
   /* Now every digit is in [0, 2^32): find the most significant set bit. */
-  int top = -1;
-  for (int i = SA_DIGITS * 32 - 1; i >= 0; --i)
-    if (sa_bit(d, i)) { top = i; break; }
-  if (top < 0) return 0.0;
+  int h = SA_DIGITS - 1;
+  while (h >= 0 && d[h] == 0) --h;
+  if (h < 0) return 0.0;
+  int top = 32 * h + (31 - __builtin_clz((uint32_t)d[h]));
   double r;
   if (top < 53) {
-    uint64_t M = 0;
-    for (int i = top; i >= 0; --i) M = (M << 1) | (uint64_t)sa_bit(d, i);
-    r = ldexp((double)M, -1074);                    /* exact */
+    r = ldexp((double)sa_bits(d, 0, top + 1), -1074);  /* exact */
   } else {
-    int lo = top - 52;                              /* keep bits [lo, top] */
-    uint64_t M = 0;
-    for (int i = top; i >= lo; --i) M = (M << 1) | (uint64_t)sa_bit(d, i);
-    int guard = sa_bit(d, lo - 1), sticky = 0;
-    for (int i = lo - 2; i >= 0 && !sticky; --i) sticky = sa_bit(d, i);
-    if (guard && (sticky || (M & 1))) M += 1;       /* nearest, ties to even */
-    r = ldexp((double)M, lo - 1074);                /* M <= 2^53: exact or inf */
+    int lo = top - 52;                                  /* keep bits [lo, top] */
+    uint64_t M = sa_bits(d, lo, 53);
+    int guard = (int)sa_bits(d, lo - 1, 1);
+    int sticky = sa_any_below(d, lo - 1);
+    if (guard && (sticky || (M & 1))) M += 1;           /* nearest, ties to even */
+    r = ldexp((double)M, lo - 1074);                    /* M <= 2^53: exact or inf */
   }
   return neg ? -r : r;
 }
@@ -309,6 +323,45 @@ int or_segmented(const or_fn *f, int dtype, const void *x, const int64_t *off,
   for (int64_t j = 0; j < num_segments; ++j) {
     if (off[j + 1] < off[j]) return -1;
     reduce_range(f, dtype, x, NULL, off[j], off[j + 1], &r[j]);
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Prefix sums                                                               */
+/* ------------------------------------------------------------------------ */
+
+int or_scan(const or_fn *f, int dtype, const void *x, int64_t n, int exclusive,
+            double *out_exact, double *out_abs, int64_t *out_int) {
+  if (!valid(f, dtype) || f->kind == OR_PRODUCT || n < 0) return -1;
+  if (dtype == OR_I32) {
+    uint64_t acc = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      int64_t v = ((const int32_t *)x)[i];
+      uint64_t t = f->kind == OR_AFFINE
+                       ? (uint64_t)f->ia * (uint64_t)v + (uint64_t)f->ib
+                       : (uint64_t)v;
+      if (exclusive && out_int) out_int[i] = (int64_t)acc;
+      acc += t;
+      if (!exclusive && out_int) out_int[i] = (int64_t)acc;
+    }
+    return 0;
+  }
+  sacc s;
+  sa_init(&s);
+  double abs_sum = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    double t = (double)or_term_f32(f, (float)widen(dtype, x, i));
+    if (exclusive) {
+      if (out_exact) out_exact[i] = sa_round(&s);
+      if (out_abs) out_abs[i] = abs_sum;
+    }
+    sa_add(&s, t);
+    abs_sum += fabs(t);
+    if (!exclusive) {
+      if (out_exact) out_exact[i] = sa_round(&s);
+      if (out_abs) out_abs[i] = abs_sum;
+    }
   }
   return 0;
 }

@@ -79,6 +79,14 @@ int or_reduce(const or_fn *f, int dtype, const void *x, const void *z,
 int or_segmented(const or_fn *f, int dtype, const void *x, const int64_t *off,
                  int64_t num_segments, or_result *r);
 
+/* Prefix sums of the terms f(x[i]) (inclusive: terms 0..i; exclusive:
+ * terms 0..i-1).  For floating-point storage out_exact[i] is the exact prefix
+ * sum rounded once to fp64 and out_abs[i] the fp64 sum of |terms| over the
+ * same range; for int32 storage out_int[i] is the prefix sum mod 2^64.
+ * Unused output pointers may be NULL.  Returns 0, or -1. */
+int or_scan(const or_fn *f, int dtype, const void *x, int64_t n, int exclusive,
+            double *out_exact, double *out_abs, int64_t *out_int);
+
 /* Exact sum of fp64 values rounded once to fp64 (IEEE results for
  * non-finite inputs). */
 double or_exact_sum(const double *v, int64_t n);

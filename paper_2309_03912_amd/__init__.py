@@ -29,7 +29,7 @@ OK, ERR_INVALID_ARGUMENT, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP = range(5)
 F32, F16, BF16, I32, I64, F64 = range(6)
 FN_IDENTITY, FN_AFFINE, FN_HORNER, FN_PRODUCT = range(4)
 ACC_PLAIN, ACC_COMPENSATED, ACC_EXACT_INT, ACC_EXACT = range(4)
-OP_MAP, OP_TRANSFORM_REDUCE, OP_SEGMENTED_REDUCE, OP_MAP_REDUCE, OP_BATCH = range(5)
+OP_MAP, OP_TRANSFORM_REDUCE, OP_SEGMENTED_REDUCE, OP_MAP_REDUCE, OP_BATCH, OP_SCAN = range(6)
 MAX_DEGREE = 16
 
 DTYPE = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16, torch.int32: I32}
@@ -41,7 +41,7 @@ FN = {"identity": FN_IDENTITY, "affine": FN_AFFINE, "horner": FN_HORNER, "produc
 # Every symbol include/hdc.h declares.
 EXPORTS = [
     "hdc_map", "hdc_transform_reduce", "hdc_segmented_reduce", "hdc_map_reduce", "hdc_batch_map_reduce",
-    "hdc_host_map", "hdc_host_transform_reduce",
+    "hdc_host_map", "hdc_host_transform_reduce", "hdc_scan",
     "hdc_workspace_size", "hdc_validate_offsets", "hdc_set_tuning", "hdc_get_tuning",
     "hdc_load_tuning", "hdc_tuning_bucket", "hdc_status_string", "hdc_last_error", "hdc_version",
 ]
@@ -94,6 +94,7 @@ def lib() -> ctypes.CDLL:
                                            ctypes.c_size_t, vp]
         L.hdc_host_map.argtypes = [P(Functor), i32, vp, vp, i64, ctypes.c_int32]
         L.hdc_host_transform_reduce.argtypes = [P(Functor), i32, vp, vp, i64, i32, vp, ctypes.c_int32]
+        L.hdc_scan.argtypes = [P(Functor), i32, vp, vp, i64, i32, ctypes.c_int32, vp, ctypes.c_size_t, vp]
         L.hdc_workspace_size.argtypes = [i32, i32, i32, i64, i64, P(ctypes.c_size_t)]
         L.hdc_validate_offsets.argtypes = [vp, i64, i64, vp]
         L.hdc_set_tuning.argtypes = [i32, i32, i32, i32, P(Tuning)]
@@ -101,7 +102,7 @@ def lib() -> ctypes.CDLL:
         L.hdc_tuning_bucket.argtypes = [i64, P(ctypes.c_int32)]
         L.hdc_load_tuning.argtypes = [ctypes.c_char_p]
         for name in ["hdc_map", "hdc_transform_reduce", "hdc_segmented_reduce", "hdc_map_reduce",
-                     "hdc_batch_map_reduce", "hdc_host_map", "hdc_host_transform_reduce",
+                     "hdc_batch_map_reduce", "hdc_host_map", "hdc_host_transform_reduce", "hdc_scan",
                      "hdc_workspace_size", "hdc_validate_offsets", "hdc_set_tuning", "hdc_get_tuning",
                      "hdc_load_tuning", "hdc_tuning_bucket"]:
             getattr(L, name).restype = st
@@ -315,6 +316,21 @@ def batch_map_reduce(xs, map_fn, reduce_fn, acc="plain", ys=None, outs=None, ws=
     _check(lib().hdc_batch_map_reduce(f, ctypes.byref(g), dt, a, table, len(xs), ws.data_ptr(), ws.numel(),
                                       _stream(xs[0])))
     return ys, outs
+
+
+def scan(x: torch.Tensor, fn, acc="plain", exclusive: bool = False, out: torch.Tensor | None = None,
+         ws: torch.Tensor | None = None) -> torch.Tensor:
+    """Prefix sums of fn(x): float32 (plain), float64 (compensated) or int64 (exact_int)."""
+    x = _gpu_tensor(x, "x")
+    a = _acc(acc)
+    dt = _dtype(x)
+    y = torch.empty(x.numel(), dtype=OUT_DTYPE[a], device=x.device) if out is None else _gpu_tensor(out, "out")
+    if ws is None:
+        ws = workspace(x.device, OP_SCAN, dt, a, x.numel())
+    f = make_functor(fn)
+    _check(lib().hdc_scan(ctypes.byref(f), dt, x.data_ptr(), y.data_ptr(), x.numel(), a, int(exclusive),
+                          ws.data_ptr(), ws.numel(), _stream(x)))
+    return y
 
 
 def _host_tensor(t: torch.Tensor, name: str) -> torch.Tensor:

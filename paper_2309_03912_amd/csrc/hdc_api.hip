@@ -71,7 +71,7 @@ namespace {
 // Tuning
 // ---------------------------------------------------------------------------
 
-constexpr int kOps = 5, kDtypes = 6, kAccs = 4, kBuckets = 4;
+constexpr int kOps = 6, kDtypes = 6, kAccs = 4, kBuckets = 4;
 std::mutex g_tune_mu;
 Tuning g_tune[kOps][kDtypes][kAccs][kBuckets];
 
@@ -124,6 +124,11 @@ hdc_status load_tuning_file(const char* path) {
 // The cache named by HDC_TUNE_CACHE is read once, before the first lookup.
 void ensure_tuning_loaded() {
   std::call_once(g_tune_once, [] {
+    // defaults that differ from the struct's: scans use 1024-thread tiles
+    // (16384 elements), so one block scans the tile sums of 2^28 elements
+    for (auto& per_dt : g_tune[HDC_OP_SCAN])
+      for (auto& per_acc : per_dt)
+        for (Tuning& t : per_acc) t.block = 1024;
     const char* p = getenv("HDC_TUNE_CACHE");
     if (p && *p) load_tuning_file(p);
   });
@@ -425,6 +430,29 @@ hdc_status hdc_host_transform_reduce(const hdc_functor* f, hdc_dtype dt, const v
   return run_host_reduce(*f, dt, x, z, n, acc, out, nthreads);
 }
 
+
+hdc_status hdc_scan(const hdc_functor* f, hdc_dtype dt, const void* x, void* y, int64_t n, hdc_accum acc,
+                    int32_t exclusive, void* workspace, size_t ws_bytes, void* stream) {
+  HDC_TRY(check_functor(f, dt, false));
+  HDC_TRY(check_acc(dt, acc));
+  if (acc == HDC_ACC_EXACT) return fail(HDC_ERR_UNSUPPORTED, "EXACT is provided for transform_reduce and map_reduce");
+  if (n < 0) return fail(HDC_ERR_INVALID_ARGUMENT, "n = %lld is negative", (long long)n);
+  if (exclusive != 0 && exclusive != 1) return fail(HDC_ERR_INVALID_ARGUMENT, "exclusive must be 0 or 1");
+  HDC_TRY(check_ptr(x, dt, n, "x"));
+  const size_t osz = acc == HDC_ACC_PLAIN ? 4 : 8;
+  if (n > 0 && !y) return fail(HDC_ERR_INVALID_ARGUMENT, "y is NULL");
+  if (y && (uintptr_t)y % osz) return fail(HDC_ERR_INVALID_ARGUMENT, "y is not aligned to its element size");
+  if (n == 0) return HDC_OK;
+  const uintptr_t xb = (uintptr_t)x, yb = (uintptr_t)y;
+  if (xb < yb + (uintptr_t)n * osz && yb < xb + (uintptr_t)n * elem_size(dt))
+    return fail(HDC_ERR_INVALID_ARGUMENT, "x and y overlap");
+  hipStream_t st = (hipStream_t)stream;
+  const Tuning t = tuning_for(HDC_OP_SCAN, dt, acc, n);
+  void* ws = nullptr;
+  HDC_TRY(resolve_workspace(workspace, ws_bytes, scan_workspace_bytes(n), st, &ws));
+  return run_scan(*f, dt, x, y, n, acc, exclusive, ws, t, st);
+}
+
 hdc_status hdc_workspace_size(int op, hdc_dtype dt, hdc_accum acc, int64_t n, int64_t num_segments,
                               size_t* bytes) {
   if (!bytes) return fail(HDC_ERR_INVALID_ARGUMENT, "bytes is NULL");
@@ -435,6 +463,9 @@ hdc_status hdc_workspace_size(int op, hdc_dtype dt, hdc_accum acc, int64_t n, in
     case HDC_OP_MAP: *bytes = 0; return HDC_OK;
     case HDC_OP_TRANSFORM_REDUCE:
     case HDC_OP_MAP_REDUCE: *bytes = reduce_workspace_bytes(); return HDC_OK;
+    case HDC_OP_SCAN:
+      *bytes = scan_workspace_bytes(n);
+      return HDC_OK;
     case HDC_OP_BATCH:
       *bytes = batch_workspace_bytes(n, num_segments);
       if (*bytes < reduce_workspace_bytes()) *bytes = reduce_workspace_bytes();  // calls run one by one reuse it

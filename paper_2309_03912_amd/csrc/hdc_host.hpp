@@ -172,6 +172,14 @@ hdc_status run_batch(const hdc_functor* fm, const hdc_functor& g, hdc_dtype dt, 
                      const hdc_batch_call* calls, const int32_t* idx, int cnt, void* ws, const Tuning& t,
                      hipStream_t st);
 
+hdc_status run_scan(const hdc_functor& f, hdc_dtype dt, const void* x, void* y, int64_t n, hdc_accum acc,
+                    int exclusive, void* ws, const Tuning& t, hipStream_t st);
+// Workspace of a scan: tile sums and tile offsets (tiles of at least 64 * 16 elements).
+inline size_t scan_workspace_bytes(int64_t n) {
+  const int64_t G = n / 1024 + 1;
+  return 2 * round_up((size_t)G * 8, 256);
+}
+
 // The host side (hdc_host_map / hdc_host_transform_reduce).
 hdc_status run_host_map(const hdc_functor& f, hdc_dtype dt, const void* x, void* y, int64_t n, int32_t nthreads);
 hdc_status run_host_reduce(const hdc_functor& f, hdc_dtype dt, const void* x, const void* z, int64_t n,

@@ -6,6 +6,7 @@
 
 #include "hdc_batch.hpp"
 #include "hdc_host.hpp"
+#include "hdc_scan.hpp"
 
 namespace hdc {
 
@@ -168,6 +169,40 @@ hdc_status launch_batch(const FM& fm, const F& f, const hdc_batch_call* calls, c
   }
   batch_combine_kernel<Acc><<<dim3((unsigned)((cnt + 3) / 4)), dim3(256), 0, st>>>(tab, partials);
   return check_launch("batch combine launch");
+}
+
+template <class F, class S, class Acc>
+hdc_status launch_scan(const F& f, const void* x, void* y, int64_t n, int exclusive, void* ws, const Tuning& t,
+                       hipStream_t st) {
+  using T = typename S::T;
+  using OutT = typename ScanOut<Acc>::T;
+  const int64_t tile = (int64_t)t.block * kScanE;
+  const int64_t G = (n + tile - 1) / tile;
+  Acc* sums = static_cast<Acc*>(ws);
+  Acc* offsets = reinterpret_cast<Acc*>(static_cast<char*>(ws) + round_up((size_t)G * sizeof(Acc), 256));
+  const bool xa = (uintptr_t)x % 16 == 0, ya = (uintptr_t)y % 16 == 0;
+  const T* xp = static_cast<const T*>(x);
+  OutT* yp = static_cast<OutT*>(y);
+  if (xa)
+    scan_tile_sums_kernel<F, S, Acc, true><<<dim3((unsigned)G), dim3(t.block), 0, st>>>(f, xp, n, sums);
+  else
+    scan_tile_sums_kernel<F, S, Acc, false><<<dim3((unsigned)G), dim3(t.block), 0, st>>>(f, xp, n, sums);
+  HDC_TRY(check_launch("scan tile-sum launch"));
+  scan_offsets_kernel<Acc><<<dim3(1), dim3(1024), 0, st>>>(sums, G, offsets);
+  HDC_TRY(check_launch("scan offset launch"));
+  if (xa && ya)
+    scan_tiles_kernel<F, S, Acc, true, true><<<dim3((unsigned)G), dim3(t.block), 0, st>>>(f, xp, n, offsets, yp,
+                                                                                         exclusive);
+  else if (xa)
+    scan_tiles_kernel<F, S, Acc, true, false><<<dim3((unsigned)G), dim3(t.block), 0, st>>>(f, xp, n, offsets, yp,
+                                                                                          exclusive);
+  else if (ya)
+    scan_tiles_kernel<F, S, Acc, false, true><<<dim3((unsigned)G), dim3(t.block), 0, st>>>(f, xp, n, offsets, yp,
+                                                                                          exclusive);
+  else
+    scan_tiles_kernel<F, S, Acc, false, false><<<dim3((unsigned)G), dim3(t.block), 0, st>>>(f, xp, n, offsets, yp,
+                                                                                           exclusive);
+  return check_launch("scan tile launch");
 }
 
 }  // namespace hdc

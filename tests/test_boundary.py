@@ -168,3 +168,21 @@ def test_host_only_callable_cannot_instantiate_a_kernel():
     assert "constraints not satisfied" in bad.stderr or "no matching" in bad.stderr
     good = _hipcc_probe(["-DPROBE_DEVICE_TAGGED"])
     assert good.returncode == 0, good.stderr
+
+
+def test_scan_rejects_bad_arguments():
+    L = hdc.lib()
+    ident = fn({"fn": "identity"})
+    need = hdc.workspace_size(hdc.OP_SCAN, hdc.F32, hdc.ACC_PLAIN, 1000)
+    assert need > 0
+    call = lambda **k: L.hdc_scan(k.get("f", ident), k.get("dt", hdc.F32), k.get("x", FAKE), k.get("y", FAKE + 65536),
+                                  k.get("n", 1000), k.get("acc", hdc.ACC_PLAIN), k.get("ex", 0), FAKE * 4,
+                                  k.get("wsb", need), None)
+    assert call(n=-1) == hdc.ERR_INVALID_ARGUMENT
+    assert call(ex=2) == hdc.ERR_INVALID_ARGUMENT
+    assert call(y=None) == hdc.ERR_INVALID_ARGUMENT
+    assert call(y=FAKE + 100) == hdc.ERR_INVALID_ARGUMENT                   # overlaps x
+    assert call(f=fn({"fn": "product"})) == hdc.ERR_UNSUPPORTED
+    assert call(acc=hdc.ACC_EXACT_INT) == hdc.ERR_UNSUPPORTED
+    assert call(wsb=need - 1) == hdc.ERR_WORKSPACE
+    assert call(n=0, x=None, y=None) == hdc.OK

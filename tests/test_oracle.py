@@ -383,3 +383,34 @@ def test_segmented_brute_force_and_empty():
 def test_segmented_rejects_decreasing_offsets():
     with pytest.raises(ValueError):
         oracle.segmented({"fn": "identity"}, torch.zeros(10), torch.tensor([0, 5, 3, 10]))
+
+
+# --------------------------------------------------------------------------
+# Prefix sums
+# --------------------------------------------------------------------------
+
+def test_scan_closed_forms():
+    n = 5000
+    ones = torch.ones(n)
+    r = oracle.scan({"fn": "identity"}, ones)
+    assert np.array_equal(r["exact"], np.arange(1, n + 1))
+    r = oracle.scan({"fn": "identity"}, ones, exclusive=True)
+    assert np.array_equal(r["exact"], np.arange(0, n))
+    xi = torch.arange(n, dtype=torch.int32)
+    r = oracle.scan({"fn": "identity"}, xi)
+    i = np.arange(n)
+    assert np.array_equal(r["isum"], i * (i + 1) // 2)                       # arithmetic series
+    r = oracle.scan({"fn": "affine", "a": 3, "b": -7}, xi, exclusive=True)
+    assert np.array_equal(r["isum"], 3 * (i * (i - 1) // 2) - 7 * i)
+
+
+def test_scan_matches_fsum_prefixes_and_reduce():
+    x = synth.uniform_pm1_f32(4, 0, 3000)
+    r = oracle.scan(HORNER, x)
+    terms = oracle.map(HORNER, x).double().tolist()
+    for k in (0, 1, 17, 1000, 2999):
+        assert r["exact"][k] == math.fsum(terms[:k + 1])
+    assert r["exact"][-1] == oracle.reduce(HORNER, x)["exact"]
+    rex = oracle.scan(HORNER, x, exclusive=True)
+    assert rex["exact"][0] == 0.0 and np.array_equal(rex["exact"][1:], r["exact"][:-1])
+    assert np.all(np.diff(r["abs_sum"]) >= 0)
