@@ -40,7 +40,7 @@ def parse():
     p.add_argument("--no-check", action="store_true", help="skip the oracle accuracy checks")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-forms", action="store_true", help="only the headline plain-FP32 step")
-    p.add_argument("--forms", default="c3,c4,c5")
+    p.add_argument("--forms", default="c3,c4,c5,scan")
     p.add_argument("--cpu-sample-log2", type=int, default=28)
     p.add_argument("--with-copy", action="store_true",
                    help="add a plain copy (identity map, f32) to each step: the reference kernel of known size "
@@ -253,6 +253,17 @@ def form_precision(args, torch, hdc, synth):
                 entry["comp_err"] = err_fields(rc, ref)
                 entry["plain_f32_err"] = err_fields(rp, ref)
             res[op] = entry
+        if dt == torch.float16:
+            # exact fp16 sums: the correctly rounded exact sum, independent of order and tuning
+            for op, arr in (("sum_x", x), ("sum_v_kappa", v)):
+                fe = lambda: hdc.transform_reduce(arr, ident, "exact")
+                te = ev_time(torch, fe)
+                entry = {"exact_ms": round(te, 5), "exact_GBps": round(gbps(2 * n, te), 1)}
+                if not args.no_check:
+                    import oracle
+                    exact = info["target"] if op == "sum_v_kappa" else oracle.reduce(ident, x)["exact"]
+                    entry["exact_bits_equal_oracle"] = fe().item() == exact
+                res[op].update(entry)
         out[name] = res
         del x, z, v, xf, zf, vf
         torch.cuda.empty_cache()
@@ -485,6 +496,27 @@ def form_graph(args, torch, hdc, synth):
     return res
 
 
+def form_scan(args, torch, hdc, synth):
+    """Prefix sums (inclusive) of p(x) over n f32 values: x is read twice, y written once."""
+    dev = torch.device("cuda", 0)
+    n = 1 << args.log2n
+    x = synth.uniform_pm1_f32(synth.seed_of(2), synth.STREAM["x"], n, dev)
+    hor = hdc.horner(synth.horner_coefficients(8))
+    y = torch.empty(n, dtype=torch.float32, device=dev)
+    ws = hdc.workspace(dev, hdc.OP_SCAN, hdc.F32, hdc.ACC_PLAIN, n)
+    t = ev_time(torch, lambda: hdc.scan(x, hor, "plain", out=y, ws=ws))
+    xi = synth.uniform_int(synth.seed_of(2), synth.STREAM["xi"], n, 20, dev)
+    yi = torch.empty(n, dtype=torch.int64, device=dev)
+    wsi = hdc.workspace(dev, hdc.OP_SCAN, hdc.I32, hdc.ACC_EXACT_INT, n)
+    ti = ev_time(torch, lambda: hdc.scan(xi, hdc.identity(), "exact_int", out=yi, ws=wsi))
+    res = {"n": n, "f32_horner_ms": round(t, 5), "f32_horner_GBps": round(gbps(12 * n, t), 1),
+           "i32_to_i64_ms": round(ti, 5), "i32_to_i64_GBps": round(gbps(16 * n, ti), 1),
+           "bytes_per_element": "f32: 4+4 read + 4 write; i32->i64: 4+4 read + 8 write"}
+    del x, y, xi, yi
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -538,6 +570,8 @@ def main():
             forms["segmented_100k_lognormal"] = form_segmented(args, torch, hdc, synth)
         if "c5" in want:
             forms["graph_64_calls"] = form_graph(args, torch, hdc, synth)
+        if "scan" in want:
+            forms["scan"] = form_scan(args, torch, hdc, synth)
         out["forms"] = forms
     print(json.dumps(out), flush=True)
 

@@ -31,10 +31,11 @@ import time
 
 import torch
 
-from . import (ACC_COMPENSATED, ACC_EXACT_INT, ACC_PLAIN, BF16, F16, F32, I32, OP_MAP, OP_MAP_REDUCE,
-               OP_SEGMENTED_REDUCE, OP_TRANSFORM_REDUCE, get_tuning, set_tuning, tuning_bucket)
+from . import (ACC_COMPENSATED, ACC_EXACT, ACC_EXACT_INT, ACC_PLAIN, BF16, F16, F32, I32, OP_BATCH, OP_MAP,
+               OP_MAP_REDUCE, OP_SCAN, OP_SEGMENTED_REDUCE, OP_TRANSFORM_REDUCE, get_tuning, set_tuning,
+               tuning_bucket)
 from . import map as hdc_map
-from . import map_reduce, segmented_reduce, transform_reduce, workspace
+from . import batch_map_reduce, map_reduce, scan, segmented_reduce, transform_reduce, workspace
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(HERE, "tuning_gfx950.txt")
@@ -76,7 +77,19 @@ class Case:
         self.y = torch.empty_like(self.x)
         accname = {ACC_PLAIN: "plain", ACC_COMPENSATED: "compensated", ACC_EXACT_INT: "exact_int"}[acc]
         self.accname = accname
-        if op == OP_SEGMENTED_REDUCE:
+        if op == OP_BATCH:
+            # `segments` holds the call sizes of the batch
+            self.xs = [_inputs(dt, m, dev, seed=10 + i) for i, m in enumerate(segments)]
+            self.ys = [torch.empty_like(v) for v in self.xs]
+            self.outs = [torch.empty((), dtype={ACC_PLAIN: torch.float32, ACC_COMPENSATED: torch.float64,
+                                                ACC_EXACT_INT: torch.int64}[acc], device=dev) for _ in self.xs]
+            self.ws = workspace(dev, op, dt, acc, sum(segments), len(segments))
+            self.bucket = tuning_bucket(n)
+        elif op == OP_SCAN:
+            self.ys = torch.empty(n, dtype={ACC_PLAIN: torch.float32, ACC_COMPENSATED: torch.float64,
+                                            ACC_EXACT_INT: torch.int64}[acc], device=dev)
+            self.ws = workspace(dev, op, dt, acc, n)
+        elif op == OP_SEGMENTED_REDUCE:
             self.off = segments.to(dev)
             S = self.off.numel() - 1
             self.ws = workspace(dev, op, dt, acc, n, S)
@@ -90,6 +103,14 @@ class Case:
             self.z = _inputs(dt, n, dev, seed=2)
 
     def run(self):
+        if self.op == OP_BATCH:
+            fn = self.ident if self.dt == I32 else self.horner
+            batch_map_reduce(self.xs, self.aff, fn, self.accname, ys=self.ys, outs=self.outs, ws=self.ws)
+            return
+        if self.op == OP_SCAN:
+            fn = self.ident if self.dt == I32 else self.horner
+            scan(self.x, fn, self.accname, out=self.ys, ws=self.ws)
+            return
         if self.op == OP_MAP:
             hdc_map(self.x, self.aff, out=self.y)
         elif self.op == OP_TRANSFORM_REDUCE:
@@ -106,6 +127,10 @@ class Case:
         transform_reduce(self.x, {"fn": "product"}, self.accname, z=self.z, out=self.out, ws=self.ws)
 
     def output(self):
+        if self.op == OP_BATCH:
+            return ([y.clone() for y in self.ys], [o.clone() for o in self.outs])
+        if self.op == OP_SCAN:
+            return self.ys.clone()
         if self.op == OP_MAP:
             return self.y.clone()
         if self.op == OP_MAP_REDUCE:
@@ -113,6 +138,11 @@ class Case:
         return self.out.clone()
 
     def agrees(self, a, b):
+        if self.op == OP_BATCH:
+            return all(self.agrees_map(p, q) for p, q in zip(a[0], b[0])) and \
+                all(self.agrees_sum(p, q) for p, q in zip(a[1], b[1]))
+        if self.op == OP_SCAN:
+            return self.agrees_sum(a, b)
         if self.op == OP_MAP:
             return torch.equal(a.view(torch.int16) if a.element_size() == 2 else a.view(torch.int32),
                                b.view(torch.int16) if b.element_size() == 2 else b.view(torch.int32))
@@ -139,11 +169,15 @@ def candidates(op, quick=False):
     unrolls = [2, 4, 8] if quick else [1, 2, 4, 8]
     gms = [4, 8, 16] if quick else [2, 4, 8, 16, 32]
     base = [dict(block=b, unroll=u, grid_mult=g) for b, u, g in itertools.product(blocks, unrolls, gms)]
+    if op == OP_BATCH:
+        return base, [dict(chunk=c) for c in [8192, 16384, 32768, 65536]]
+    if op == OP_SCAN:
+        return [dict(block=b) for b in [256, 512, 1024]]
     if op != OP_SEGMENTED_REDUCE:
         return base
     seg = [dict(chunk=c, small_seg=s, seg_per_wave=w)
            for c, s, w in itertools.product([2048, 4096, 8192] if quick else [1024, 2048, 4096, 8192, 16384],
-                                            [64, 128, 256], [4, 8, 16])]
+                                            [64, 128, 256, 512], [2, 4, 8, 16])]
     # two stages: geometry at the default segment split, then the split at the best geometry
     return base, seg
 
@@ -151,7 +185,7 @@ def candidates(op, quick=False):
 def tune_case(case: Case, quick=False, reps=5, rounds=3, log=print):
     op, dt, acc, b = case.key()
     cands = candidates(op, quick)
-    stages = [cands] if op != OP_SEGMENTED_REDUCE else list(cands)
+    stages = list(cands) if op in (OP_SEGMENTED_REDUCE, OP_BATCH) else [cands]
     best = get_tuning(op, dt, acc, b)
     for stage in stages:
         trial = [dict(best, **c) for c in stage]
@@ -208,6 +242,11 @@ def default_cases(dev, quick=False, log2n=28):
     off = synth.offsets_from_lengths(L)
     cases += [Case(OP_SEGMENTED_REDUCE, F32, ACC_PLAIN, int(off[-1]), dev, off),
               Case(OP_SEGMENTED_REDUCE, F32, ACC_COMPENSATED, int(off[-1]), dev, off)]
+    # the 64-call graph workload as two grouped batches (fp16 and int32 halves)
+    sizes = synth.call_sizes(synth.seed_of(5))
+    cases += [Case(OP_BATCH, F16, ACC_COMPENSATED, sum(sizes[0::2]) // 32, dev, sizes[0::2]),
+              Case(OP_BATCH, I32, ACC_EXACT_INT, sum(sizes[1::2]) // 32, dev, sizes[1::2])]
+    cases += [Case(OP_SCAN, F32, ACC_PLAIN, n, dev), Case(OP_SCAN, I32, ACC_EXACT_INT, n, dev)]
     # batched calls: every size bucket of the fused map + reduce
     for m in ([1 << 14, 1 << 18, 1 << 22, 1 << 25] if not quick else [1 << 18, 1 << 25]):
         cases += [Case(OP_MAP_REDUCE, F16, ACC_COMPENSATED, m, dev), Case(OP_MAP_REDUCE, I32, ACC_EXACT_INT, m, dev),

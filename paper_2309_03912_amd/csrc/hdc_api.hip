@@ -129,6 +129,10 @@ void ensure_tuning_loaded() {
     for (auto& per_dt : g_tune[HDC_OP_SCAN])
       for (auto& per_acc : per_dt)
         for (Tuning& t : per_acc) t.block = 1024;
+    // grouped batches fold chunks of 32768 elements (one partial per chunk)
+    for (auto& per_dt : g_tune[HDC_OP_BATCH])
+      for (auto& per_acc : per_dt)
+        for (Tuning& t : per_acc) t.chunk = 32768;
     const char* p = getenv("HDC_TUNE_CACHE");
     if (p && *p) load_tuning_file(p);
   });
