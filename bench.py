@@ -517,6 +517,24 @@ def form_scan(args, torch, hdc, synth):
     return res
 
 
+def measured_traffic(op_name):
+    """HBM bytes per launch of `op_name` from the committed counter summary, or None when the kernel
+    sources changed since the counters were taken (or the op was not measured)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_headline.json")
+    try:
+        t = json.load(open(path))
+        h = hashlib.sha256()
+        for f in t["source_files"]:
+            h.update(os.path.basename(f).encode())
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest() != t["source_sha256"]:
+            return None
+        return t["kernels"][op_name]["traffic_bytes"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -553,7 +571,8 @@ def main():
                    "n": h["n"], "step_bytes": h["step_bytes"]},
         "frac_of_peak": round(value / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "achieved": d["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(d["GBps"] / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dominant,
+                     "frac": round(d["GBps"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dominant),
+                     "kernel": dominant,
                      "bytes_per_launch": d["bytes"], "launch_ms": d["ms"]},
         "per_op": per_op,
     }
