@@ -125,27 +125,28 @@ __global__ __launch_bounds__(1024) void batch_kernel(FM fm, F f, BatchTable t, A
   }
 }
 
-// One wavefront per call folds that call's chunk partials in chunk order.
+// One block per call folds that call's chunk partials: thread-strided in
+// chunk order, then the fixed block reduction.
 template <class Acc>
 __global__ __launch_bounds__(256) void batch_combine_kernel(BatchTable t, const Acc* partials) {
-  const int lane = threadIdx.x & 63;
-  const int w = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
-  if (w >= t.count) return;
-  const int64_t lo = t.prefix[w], hi = t.prefix[w + 1];
-  void* out = t.call[w].out;
+  const int c = blockIdx.x;
+  const int64_t lo = t.prefix[c], hi = t.prefix[c + 1];
+  void* out = t.call[c].out;
   if constexpr (std::is_same_v<Acc, CompAcc>) {
+    __shared__ double lds[kMaxWaves];
     double d = 0.0;
-    for (int64_t k = lo + lane; k < hi; k += 64) {
+    for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
       const CompAcc q = partials[k];
       d += __builtin_isfinite(q.s) ? (double)q.s + (double)q.c : (double)q.s;
     }
-    d = wave_reduce(d, AddF64{});
-    if (lane == 0) *static_cast<double*>(out) = d;
+    d = block_reduce(d, AddF64{}, lds);
+    if (threadIdx.x == 0) *static_cast<double*>(out) = d;
   } else {
+    __shared__ Acc lds[kMaxWaves];
     Acc a = Acc::zero();
-    for (int64_t k = lo + lane; k < hi; k += 64) a = Acc::merge(a, partials[k]);
-    a = wave_reduce(a, MergeOp<Acc>{});
-    if (lane == 0) {
+    for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) a = Acc::merge(a, partials[k]);
+    a = block_reduce(a, MergeOp<Acc>{}, lds);
+    if (threadIdx.x == 0) {
       if constexpr (std::is_same_v<Acc, PlainAcc>)
         *static_cast<float*>(out) = a.s;
       else

@@ -55,8 +55,8 @@ constexpr int64_t kMinChunk = 1024;
 
 // Layout of the segmented workspace for a given chunk (sections 256-byte aligned).
 struct SegLayout {
-  size_t cnt, full, part, long_base, long_list, partials, bytes;
-  int64_t cap_full, cap_part, cap_partials;
+  size_t cnt, block_tot, full, part, long_base, long_list, partials, bytes;
+  int64_t cap_full, cap_part, cap_partials, plan_blocks;
 };
 
 // Partial slots of a grouped batch: at most total/chunk + count chunks.
@@ -69,8 +69,10 @@ inline SegLayout seg_layout(int64_t total, int64_t S, int64_t chunk) {
   l.cap_full = total / chunk + 1;
   l.cap_part = S > 0 ? S : 1;
   l.cap_partials = l.cap_full + l.cap_part;
+  l.plan_blocks = (S + kPlanBlock - 1) / kPlanBlock;
   size_t o = 0;
   l.cnt = o;       o += round_up(sizeof(SegCounters), 256);
+  l.block_tot = o; o += round_up((size_t)(l.plan_blocks + 1) * sizeof(SegCounters), 256);
   l.full = o;      o += round_up((size_t)l.cap_full * sizeof(SegPiece), 256);
   l.part = o;      o += round_up((size_t)l.cap_part * sizeof(SegPiece), 256);
   l.long_base = o; o += round_up((size_t)l.cap_part * sizeof(int32_t), 256);

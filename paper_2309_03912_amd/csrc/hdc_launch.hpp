@@ -84,6 +84,7 @@ hdc_status launch_segmented(const F& f, const void* x, const int64_t* off, int64
   char* base = static_cast<char*>(ws);
   SegPlan p;
   p.cnt = reinterpret_cast<SegCounters*>(base + l.cnt);
+  p.block_tot = reinterpret_cast<SegCounters*>(base + l.block_tot);
   p.full_list = reinterpret_cast<SegPiece*>(base + l.full);
   p.part_list = reinterpret_cast<SegPiece*>(base + l.part);
   p.long_base = reinterpret_cast<int32_t*>(base + l.long_base);
@@ -96,9 +97,11 @@ hdc_status launch_segmented(const F& f, const void* x, const int64_t* off, int64
   p.small_seg = t.small_seg;
   p.spw = t.seg_per_wave;
 
-  seg_reset_kernel<<<dim3(1), dim3(64), 0, st>>>(p.cnt);
-  HDC_TRY(check_launch("segmented reset launch"));
-  seg_plan_kernel<<<dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, st>>>(off, nseg, p);
+  seg_count_kernel<<<dim3((unsigned)l.plan_blocks), dim3(kPlanBlock), 0, st>>>(off, nseg, p);
+  HDC_TRY(check_launch("segmented count launch"));
+  seg_count_scan_kernel<<<dim3(1), dim3(1024), 0, st>>>(l.plan_blocks, p);
+  HDC_TRY(check_launch("segmented count-scan launch"));
+  seg_write_kernel<<<dim3((unsigned)l.plan_blocks), dim3(kPlanBlock), 0, st>>>(off, nseg, p);
   HDC_TRY(check_launch("segmented plan launch"));
 
   // Persistent grid: enough wavefronts to fill the chip, never more than the
@@ -167,7 +170,7 @@ hdc_status launch_batch(const FM& fm, const F& f, const hdc_batch_call* calls, c
     }
     HDC_TRY(check_launch("batch launch"));
   }
-  batch_combine_kernel<Acc><<<dim3((unsigned)((cnt + 3) / 4)), dim3(256), 0, st>>>(tab, partials);
+  batch_combine_kernel<Acc><<<dim3((unsigned)cnt), dim3(256), 0, st>>>(tab, partials);
   return check_launch("batch combine launch");
 }
 

@@ -166,7 +166,11 @@ __global__ __launch_bounds__(1024) void scan_offsets_kernel(const Acc* sums, int
   }
 }
 
-// Pass C: scan every tile and add its offset.
+// Pass C: scan every tile and add its offset.  Each thread restarts from its
+// offset (tile offset + the totals of the threads before it) and adds its
+// terms in order; the outputs go out as 16-byte stores.  The stores of one
+// wavefront are 64 or 128 bytes apart, so they use the cache (which merges
+// them into whole lines) rather than the non-temporal path.
 template <class F, class S, class Acc, bool kAligned, bool kOutAligned>
   requires device_callable<F>
 __global__ __launch_bounds__(1024) void scan_tiles_kernel(F f, const elem_t<S>* x, int64_t n, const Acc* offsets,
@@ -177,16 +181,37 @@ __global__ __launch_bounds__(1024) void scan_tiles_kernel(F f, const elem_t<S>* 
   const int64_t i0 = (int64_t)blockIdx.x * T + (int64_t)threadIdx.x * kScanE;
   elem_t<S> v[kScanE];
   scan_load<S, kAligned>(x, n, i0, v);
-  Acc run[kScanE];
-  const Acc mine = scan_thread<F, S, Acc, true>(f, v, i0, n, run);
-  Acc total;
-  const Acc before = block_exclusive_scan_acc(mine, lds, &total);
-  const Acc start = Acc::merge(offsets[blockIdx.x], before);
   OutT o[kScanE];
+  if constexpr (!std::is_same_v<S, I32>) {
+    float t[kScanE];
 #pragma unroll
-  for (int k = 0; k < kScanE; ++k) {
-    const Acc prev = k == 0 ? Acc::zero() : run[k - 1];
-    o[k] = ScanOut<Acc>::value(Acc::merge(start, exclusive ? prev : run[k]));
+    for (int k = 0; k < kScanE; ++k) t[k] = S::widen(v[k]);
+    eval_batch(f, t);  // once: the terms serve the thread total and the outputs
+    Acc mine = Acc::zero();
+#pragma unroll
+    for (int k = 0; k < kScanE; ++k)
+      if (i0 + k < n) mine.add(t[k]);
+    Acc total;
+    const Acc before = block_exclusive_scan_acc(mine, lds, &total);
+    Acc a = Acc::merge(offsets[blockIdx.x], before);
+#pragma unroll
+    for (int k = 0; k < kScanE; ++k) {
+      const OutT prev = ScanOut<Acc>::value(a);
+      if (i0 + k < n) a.add(t[k]);
+      o[k] = exclusive ? prev : ScanOut<Acc>::value(a);
+    }
+  } else {
+    Acc unused[kScanE];
+    const Acc mine = scan_thread<F, S, Acc, false>(f, v, i0, n, unused);
+    Acc total;
+    const Acc before = block_exclusive_scan_acc(mine, lds, &total);
+    Acc a = Acc::merge(offsets[blockIdx.x], before);
+#pragma unroll
+    for (int k = 0; k < kScanE; ++k) {
+      const OutT prev = ScanOut<Acc>::value(a);
+      if (i0 + k < n) fold_elem<F, S>(a, f, v[k], v[k]);
+      o[k] = exclusive ? prev : ScanOut<Acc>::value(a);
+    }
   }
   if (kOutAligned && i0 + kScanE <= n) {
     constexpr int PER = 16 / sizeof(OutT);
@@ -194,7 +219,7 @@ __global__ __launch_bounds__(1024) void scan_tiles_kernel(F f, const elem_t<S>* 
     for (int q = 0; q < kScanE / PER; ++q) {
       u32x4 w;
       __builtin_memcpy(&w, &o[q * PER], 16);
-      __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(y + i0 + q * PER));
+      *reinterpret_cast<u32x4*>(y + i0 + q * PER) = w;
     }
   } else {
 #pragma unroll

@@ -7,13 +7,15 @@
 //   * every other segment is cut into pieces of `chunk` elements; a segment
 //     of one piece writes its result directly, a longer one writes one
 //     partial per piece, folded afterwards in piece order.
-// The plan pass builds two piece lists (full pieces, then the short last
-// pieces) with block-aggregated atomics.  The persistent pass walks full
-// pieces, short pieces, then small-segment groups, round-robin over its
-// wavefronts: equal-cost items first keeps the static split balanced.
-// Where an item lands in a list depends on atomic order, but every result
-// is computed over a fixed element range in a fixed order, so the output is
-// reproducible bit for bit.
+// The plan builds two piece lists (full pieces, then the short last pieces)
+// without atomics: a count pass folds per-block totals, one block scans them,
+// and a write pass places every entry at its block base plus its prefix
+// within the block -- three short launches whose list order is fixed.  The
+// persistent pass walks full pieces, short pieces, then small-segment
+// groups, round-robin over its wavefronts (equal-cost items first keeps the
+// static split balanced), prefetching the next item's descriptor and offsets
+// while the current one streams.  Every result is computed over a fixed
+// element range in a fixed order, so the output is reproducible bit for bit.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,6 +26,7 @@
 #include "hdc_device.hpp"
 #include "hdc_functors.hpp"
 #include "hdc_kernels.hpp"
+#include "hdc_scan.hpp"
 
 namespace hdc {
 
@@ -32,16 +35,21 @@ struct SegPiece {
   int32_t k;  // piece index within the segment
 };
 
-// Counters at the head of the segmented workspace.
+// Totals of the plan: list lengths and partial slots handed out.
 struct SegCounters {
   uint32_t full;      // entries of the full-piece list
   uint32_t part;      // entries of the short-piece list
   uint32_t partials;  // partial slots handed out to multi-piece segments
   uint32_t longs;     // entries of the multi-piece segment list
+  __host__ __device__ static SegCounters zero() { return {0u, 0u, 0u, 0u}; }
+  __host__ __device__ static SegCounters merge(SegCounters a, SegCounters b) {
+    return {a.full + b.full, a.part + b.part, a.partials + b.partials, a.longs + b.longs};
+  }
 };
 
 struct SegPlan {
   SegCounters* cnt;
+  SegCounters* block_tot;   // per plan block: its totals, then its exclusive base
   SegPiece* full_list;   // capacity cap_full
   SegPiece* part_list;   // capacity cap_part
   int32_t* long_base;    // per segment: first partial slot (multi-piece only)
@@ -53,74 +61,76 @@ struct SegPlan {
   int32_t spw;           // small segments per wavefront (power of two, <= 64)
 };
 
-static __global__ void seg_reset_kernel(SegCounters* c) {
-  if (threadIdx.x == 0) *c = SegCounters{0, 0, 0, 0};
+constexpr int kPlanBlock = 256;
+
+// What segment j contributes to the plan.
+struct SegShape {
+  int64_t L, pieces, nfull;
+  bool big;
+  SegCounters want;
+};
+
+__device__ __forceinline__ SegShape seg_shape(const int64_t* __restrict__ off, int64_t S, const SegPlan& p,
+                                              int64_t j) {
+  SegShape r{};
+  if (j < S) r.L = off[j + 1] - off[j];
+  r.big = j < S && r.L > p.small_seg;
+  r.pieces = r.big ? (r.L + p.chunk - 1) / p.chunk : 0;
+  r.nfull = r.pieces > 1 ? r.L / p.chunk : 0;
+  r.want.full = (uint32_t)r.nfull;
+  r.want.part = r.big && (r.pieces == 1 || r.L % p.chunk != 0) ? 1u : 0u;
+  r.want.partials = r.pieces > 1 ? (uint32_t)r.pieces : 0u;
+  r.want.longs = r.pieces > 1 ? 1u : 0u;
+  return r;
 }
 
-// Exclusive prefix sum over a block of the 32-bit values `v`; returns the
-// thread's prefix and writes the block total to *total (all threads).
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* lds, uint32_t* total) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  uint32_t incl = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t t = __shfl_up(incl, d, 64);
-    if (lane >= d) incl += t;
-  }
-  if (lane == 63) lds[wid] = incl;
-  __syncthreads();
-  uint32_t before = 0, all = 0;
-  for (int i = 0; i < nw; ++i) {
-    const uint32_t w = lds[i];
-    if (i < wid) before += w;
-    all += w;
-  }
-  __syncthreads();
-  *total = all;
-  return before + incl - v;
-}
-
-// One thread per segment.
-static __global__ __launch_bounds__(256) void seg_plan_kernel(const int64_t* __restrict__ off, int64_t S, SegPlan p) {
-  __shared__ uint32_t lds[kMaxWaves];
-  __shared__ uint32_t bases[4];
+// Plan pass 1: per-block totals.
+static __global__ __launch_bounds__(kPlanBlock) void seg_count_kernel(const int64_t* __restrict__ off, int64_t S,
+                                                                      SegPlan p) {
+  __shared__ SegCounters lds[kMaxWaves];
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t L = 0;
-  if (j < S) L = off[j + 1] - off[j];
-  const bool big = j < S && L > p.small_seg;
-  const int64_t pieces = big ? (L + p.chunk - 1) / p.chunk : 0;
-  const int64_t nfull = pieces > 1 ? L / p.chunk : 0;
-  const uint32_t want_full = (uint32_t)nfull;
-  const uint32_t want_part = big && (pieces == 1 || L % p.chunk != 0) ? 1u : 0u;
-  const uint32_t want_slots = pieces > 1 ? (uint32_t)pieces : 0u;
-  const uint32_t want_long = pieces > 1 ? 1u : 0u;
+  const SegShape sh = seg_shape(off, S, p, j);
+  SegCounters total;
+  (void)block_exclusive_scan_acc(sh.want, lds, &total);
+  if (threadIdx.x == 0) p.block_tot[blockIdx.x] = total;
+}
 
-  uint32_t tot_full, tot_part, tot_slots, tot_long;
-  const uint32_t pre_full = block_exclusive_scan(want_full, lds, &tot_full);
-  const uint32_t pre_part = block_exclusive_scan(want_part, lds, &tot_part);
-  const uint32_t pre_slots = block_exclusive_scan(want_slots, lds, &tot_slots);
-  const uint32_t pre_long = block_exclusive_scan(want_long, lds, &tot_long);
-  if (threadIdx.x == 0) {
-    bases[0] = tot_full ? atomicAdd(&p.cnt->full, tot_full) : 0;
-    bases[1] = tot_part ? atomicAdd(&p.cnt->part, tot_part) : 0;
-    bases[2] = tot_slots ? atomicAdd(&p.cnt->partials, tot_slots) : 0;
-    bases[3] = tot_long ? atomicAdd(&p.cnt->longs, tot_long) : 0;
+// Plan pass 2 (one block): exclusive scan of the block totals in place, and
+// the grand totals into p.cnt.
+static __global__ __launch_bounds__(1024) void seg_count_scan_kernel(int64_t nblocks, SegPlan p) {
+  __shared__ SegCounters lds[kMaxWaves];
+  SegCounters carry = SegCounters::zero();
+  for (int64_t base = 0; base < nblocks; base += blockDim.x) {
+    const int64_t b = base + threadIdx.x;
+    const SegCounters v = b < nblocks ? p.block_tot[b] : SegCounters::zero();
+    SegCounters total;
+    const SegCounters before = block_exclusive_scan_acc(v, lds, &total);
+    if (b < nblocks) p.block_tot[b] = SegCounters::merge(carry, before);
+    carry = SegCounters::merge(carry, total);
   }
-  __syncthreads();
-  if (!big) return;
-  const int64_t slot0 = (int64_t)bases[2] + pre_slots;
-  if (pieces > 1) {
-    const int64_t li = (int64_t)bases[3] + pre_long;
-    p.long_base[j] = slot0 + pieces <= p.cap_partials ? (int32_t)slot0 : -1;
+  if (threadIdx.x == 0) *p.cnt = carry;
+}
+
+// Plan pass 3: every segment writes its entries at its block's base plus its
+// prefix within the block.
+static __global__ __launch_bounds__(kPlanBlock) void seg_write_kernel(const int64_t* __restrict__ off, int64_t S,
+                                                                      SegPlan p) {
+  __shared__ SegCounters lds[kMaxWaves];
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const SegShape sh = seg_shape(off, S, p, j);
+  SegCounters total;
+  const SegCounters pre = SegCounters::merge(p.block_tot[blockIdx.x],
+                                             block_exclusive_scan_acc(sh.want, lds, &total));
+  if (!sh.big) return;
+  if (sh.pieces > 1) {
+    const int64_t slot0 = pre.partials, li = pre.longs;
+    p.long_base[j] = slot0 + sh.pieces <= p.cap_partials ? (int32_t)slot0 : -1;
     if (li < p.cap_part) p.long_list[li] = (int32_t)j;
   }
-  const int64_t f0 = (int64_t)bases[0] + pre_full;
-  for (int64_t k = 0; k < nfull; ++k)
+  const int64_t f0 = pre.full;
+  for (int64_t k = 0; k < sh.nfull; ++k)
     if (f0 + k < p.cap_full) p.full_list[f0 + k] = SegPiece{(int32_t)j, (int32_t)k};
-  if (want_part) {
-    const int64_t q = (int64_t)bases[1] + pre_part;
-    if (q < p.cap_part) p.part_list[q] = SegPiece{(int32_t)j, (int32_t)nfull};
-  }
+  if (sh.want.part && (int64_t)pre.part < p.cap_part) p.part_list[pre.part] = SegPiece{(int32_t)j, (int32_t)sh.nfull};
 }
 
 // Final value of a fold state as stored in `out`.
@@ -196,6 +206,7 @@ __device__ __forceinline__ Acc wave_fold_range(const F& f, const elem_t<S>* __re
 }
 
 // The persistent pass: every wavefront walks items w, w + W, w + 2W, ...
+// (wavefront-uniform indices, so descriptors and offsets are scalar loads).
 template <class F, class S, class Acc, int U>
   requires device_callable<F>
 __global__ __launch_bounds__(1024) void seg_items_kernel(F f, const elem_t<S>* __restrict__ x,
@@ -203,78 +214,104 @@ __global__ __launch_bounds__(1024) void seg_items_kernel(F f, const elem_t<S>* _
                                                          void* out) {
   const int lane = threadIdx.x & 63;
   const int64_t wpb = blockDim.x >> 6;
-  const int64_t w = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
+  const int64_t w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * wpb + (threadIdx.x >> 6)));
   const int64_t W = (int64_t)gridDim.x * wpb;
   const int64_t cf = p.cnt->full, cp = p.cnt->part;
   const int64_t nfull = cf < p.cap_full ? cf : p.cap_full;
   const int64_t npart = cp < p.cap_part ? cp : p.cap_part;
+  const int64_t npieces = nfull + npart;
   const int64_t ngroups = (S_ + p.spw - 1) / p.spw;
-  const int64_t nitems = nfull + npart + ngroups;
+  const int64_t nitems = npieces + ngroups;
   Acc* partials = static_cast<Acc*>(p.partials);
+  auto piece_at = [&](int64_t i) -> SegPiece { return i < nfull ? p.full_list[i] : p.part_list[i - nfull]; };
+  auto valid = [&](const SegPiece& pc) { return pc.seg >= 0 && pc.seg < S_; };
 
-  for (int64_t i = w; i < nitems; i += W) {
-    if (i < nfull + npart) {
-      const SegPiece pc = i < nfull ? p.full_list[i] : p.part_list[i - nfull];
-      const int64_t j = pc.seg;
-      if (j < 0 || j >= S_) continue;
-      const int64_t lo = off[j], hi = off[j + 1];
-      const int64_t s = lo + (int64_t)pc.k * p.chunk;
-      const int64_t e = min(hi, s + p.chunk);
+  // Pieces, software-pipelined: the descriptor two items ahead and the
+  // offsets one item ahead are loaded before the current item streams.
+  int64_t i = w;
+  SegPiece cur{-1, 0}, nxt{-1, 0};
+  int64_t clo = 0, chi = 0;
+  if (i < npieces) {
+    cur = piece_at(i);
+    if (valid(cur)) {
+      clo = off[cur.seg];
+      chi = off[cur.seg + 1];
+    }
+  }
+  if (i + W < npieces) nxt = piece_at(i + W);
+  for (; i < npieces; i += W) {
+    int64_t nlo = 0, nhi = 0;
+    SegPiece nn{-1, 0};
+    if (i + W < npieces && valid(nxt)) {
+      nlo = off[nxt.seg];
+      nhi = off[nxt.seg + 1];
+    }
+    if (i + 2 * W < npieces) nn = piece_at(i + 2 * W);
+    if (valid(cur)) {
+      const int64_t j = cur.seg;
+      const int64_t s = clo + (int64_t)cur.k * p.chunk;
+      const int64_t e = chi < s + p.chunk ? chi : s + p.chunk;
       const Acc r = wave_fold_range<F, S, Acc, U>(f, x, s, e, lane);
       if (lane == 0) {
-        if (hi - lo <= p.chunk) {
+        if (chi - clo <= p.chunk) {
           store_result<Acc>(out, j, r);
         } else {
           const int64_t base = p.long_base[j];
-          if (base >= 0 && base + pc.k < p.cap_partials) partials[base + pc.k] = r;
+          if (base >= 0 && base + cur.k < p.cap_partials) partials[base + cur.k] = r;
         }
       }
-    } else {
-      // A group of spw consecutive segments; 64/spw lanes per segment.
-      const int64_t g = i - nfull - npart;
-      const int lps = 64 / p.spw;
-      const int sub = lane / lps, li = lane % lps;
-      const int64_t j = g * p.spw + sub;
-      Acc a = Acc::zero();
-      bool mine = false;
-      if (j < S_) {
-        const int64_t lo = off[j], hi = off[j + 1];
-        mine = hi - lo <= p.small_seg;
-        if (mine) {
-          constexpr int B = 4;
-          for (int64_t e0 = lo + li; e0 < hi; e0 += B * lps) {
-            elem_t<S> v[B];
+    }
+    cur = nxt;
+    clo = nlo;
+    chi = nhi;
+    nxt = nn;
+  }
+
+  // Small-segment groups: spw consecutive segments, 64/spw lanes each.
+  const int64_t g0 = i - npieces;
+  for (int64_t g = g0; g < ngroups; g += W) {
+    const int lps = 64 / p.spw;
+    const int sub = lane / lps, li = lane % lps;
+    const int64_t j = g * p.spw + sub;
+    Acc a = Acc::zero();
+    bool mine = false;
+    if (j < S_) {
+      const int64_t lo = off[j], hi = off[j + 1];
+      mine = hi - lo <= p.small_seg;
+      if (mine) {
+        constexpr int B = 4;
+        for (int64_t e0 = lo + li; e0 < hi; e0 += B * lps) {
+          elem_t<S> v[B];
 #pragma unroll
-            for (int b = 0; b < B; ++b) v[b] = e0 + b * lps < hi ? x[e0 + b * lps] : elem_t<S>{};
-            if constexpr (!std::is_same_v<S, I32>) {
-              float t[B];
+          for (int b = 0; b < B; ++b) v[b] = e0 + b * lps < hi ? x[e0 + b * lps] : elem_t<S>{};
+          if constexpr (!std::is_same_v<S, I32>) {
+            float t[B];
 #pragma unroll
-              for (int b = 0; b < B; ++b) t[b] = S::widen(v[b]);
-              eval_batch(f, t);
+            for (int b = 0; b < B; ++b) t[b] = S::widen(v[b]);
+            eval_batch(f, t);
 #pragma unroll
-              for (int b = 0; b < B; ++b)
-                if (e0 + b * lps < hi) a.add(t[b]);
-            } else {
+            for (int b = 0; b < B; ++b)
+              if (e0 + b * lps < hi) a.add(t[b]);
+          } else {
 #pragma unroll
-              for (int b = 0; b < B; ++b)
-                if (e0 + b * lps < hi) fold_elem<F, S>(a, f, v[b], v[b]);
-            }
+            for (int b = 0; b < B; ++b)
+              if (e0 + b * lps < hi) fold_elem<F, S>(a, f, v[b], v[b]);
           }
         }
       }
-      // Reduce within each group of lps lanes (fixed butterfly order).
-      for (int d = 1; d < lps; d <<= 1) {
-        Acc o;
-        constexpr int W32 = sizeof(Acc) / 4;
-        int wv[W32];
-        __builtin_memcpy(wv, &a, sizeof(Acc));
-#pragma unroll
-        for (int q = 0; q < W32; ++q) wv[q] = __shfl_xor(wv[q], d, 64);
-        __builtin_memcpy(&o, wv, sizeof(Acc));
-        a = (li & d) ? Acc::merge(o, a) : Acc::merge(a, o);
-      }
-      if (mine && li == 0) store_result<Acc>(out, j, a);
     }
+    // Reduce within each group of lps lanes (fixed butterfly order).
+    for (int d = 1; d < lps; d <<= 1) {
+      Acc o;
+      constexpr int W32 = sizeof(Acc) / 4;
+      int wv[W32];
+      __builtin_memcpy(wv, &a, sizeof(Acc));
+#pragma unroll
+      for (int q = 0; q < W32; ++q) wv[q] = __shfl_xor(wv[q], d, 64);
+      __builtin_memcpy(&o, wv, sizeof(Acc));
+      a = (li & d) ? Acc::merge(o, a) : Acc::merge(a, o);
+    }
+    if (mine && li == 0) store_result<Acc>(out, j, a);
   }
 }
 
