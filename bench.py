@@ -45,7 +45,7 @@ def parse():
     p.add_argument("--with-copy", action="store_true",
                    help="add a plain copy (identity map, f32) to each step: the reference kernel of known size "
                         "that calibrates the HBM traffic counters")
-    p.add_argument("--replays", type=int, default=200)
+    p.add_argument("--replays", type=int, default=1000)
     return p.parse_args()
 
 

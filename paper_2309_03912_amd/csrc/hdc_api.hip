@@ -17,12 +17,11 @@
 #include <mutex>
 #include <string>
 #include <utility>
+#include <vector>
 
 #include "hdc.h"
 #include "hdc_batch.hpp"
 #include "hdc_host.hpp"
-
-using namespace hdc;
 
 namespace hdc {
 
@@ -42,11 +41,10 @@ hdc_status fail(hdc_status s, const char* fmt, ...) {
   return s;
 }
 
-
 namespace {
 constexpr int kMaxDevices = 64;
-int g_cus[kMaxDevices];
-}  // namespace  // 0 = not queried yet
+int g_cus[kMaxDevices];  // compute units per device; 0 = not queried yet
+}  // namespace
 
 hdc_status compute_units(int* cus) {
   int dev = 0;
@@ -64,6 +62,8 @@ hdc_status compute_units(int* cus) {
 }
 
 }  // namespace hdc
+
+using namespace hdc;
 
 namespace {
 
@@ -87,6 +87,7 @@ bool valid_class(int op, int dt, int acc, int bucket) {
   return op >= 0 && op < kOps && dt >= 0 && dt < kDtypes && acc >= 0 && acc < kAccs && bucket >= -1 &&
          bucket < kBuckets;
 }
+
 std::once_flag g_tune_once;
 
 bool valid_tuning(const Tuning& t) {
@@ -121,7 +122,9 @@ hdc_status load_tuning_file(const char* path) {
   return st;
 }
 
-// The cache named by HDC_TUNE_CACHE is read once, before the first lookup.
+// Defaults are set, and the cache named by HDC_TUNE_CACHE read, once: before
+// the first lookup and before any explicit load or set, so neither can be
+// overwritten by the defaults afterwards.
 void ensure_tuning_loaded() {
   std::call_once(g_tune_once, [] {
     // defaults that differ from the struct's: scans use 1024-thread tiles
@@ -154,6 +157,10 @@ struct InternalWs {
 };
 std::mutex g_ws_mu;
 std::map<std::pair<int, void*>, InternalWs> g_ws;
+// Buffers replaced by a larger one are kept until the process ends: work
+// already enqueued (possibly by another host thread on the same stream) may
+// still use them.  Growth at least doubles, so this at most doubles the total.
+std::vector<void*> g_ws_retired;
 
 // Resolve the workspace of a call: the caller's, or the library's buffer for
 // (device, stream), grown when needed and allowed.
@@ -177,18 +184,12 @@ hdc_status resolve_workspace(void* ws, size_t ws_bytes, size_t need, hipStream_t
     if (cs != hipStreamCaptureStatusNone)
       return fail(HDC_ERR_WORKSPACE, "the library workspace must grow, which is impossible while the stream is "
                                      "being captured: pass a workspace");
-    if (w.ptr) {
-      e = hipStreamSynchronize(stream);  // the old buffer may still be in use
-      if (e != hipSuccess) return fail(HDC_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
-      (void)hipFree(w.ptr);
-      w.ptr = nullptr;
-      w.bytes = 0;
-    }
-    size_t bytes = round_up(need, 1 << 20);
-    e = hipMalloc(&w.ptr, bytes);
+    size_t bytes = round_up(need > 2 * w.bytes ? need : 2 * w.bytes, 1 << 20);
+    void* fresh = nullptr;
+    e = hipMalloc(&fresh, bytes);
     if (e != hipSuccess) return fail(HDC_ERR_HIP, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
-    e = hipMemset(w.ptr, 0, bytes);
-    if (e != hipSuccess) return fail(HDC_ERR_HIP, "hipMemset: %s", hipGetErrorString(e));
+    if (w.ptr) g_ws_retired.push_back(w.ptr);
+    w.ptr = fresh;
     w.bytes = bytes;
   }
   *out = w.ptr;
@@ -551,6 +552,7 @@ hdc_status hdc_tuning_bucket(int64_t n, int32_t* bucket) {
 }
 
 hdc_status hdc_load_tuning(const char* path) {
+  ensure_tuning_loaded();
   if (!path) path = getenv("HDC_TUNE_CACHE");
   if (!path || !*path) return HDC_OK;
   return load_tuning_file(path);
