@@ -89,7 +89,7 @@ __device__ __forceinline__ void scan_load(const elem_t<S>* x, int64_t n, int64_t
     constexpr int NV = kScanE / S::kVec;
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-      const Vec<S> a = load16<S>(x + i0 + q * S::kVec);
+      const Vec<S> a = load16_cached<S>(x + i0 + q * S::kVec);  // a lane reads 64 contiguous bytes
 #pragma unroll
       for (int k = 0; k < S::kVec; ++k) v[q * S::kVec + k] = a.e[k];
     }
