@@ -57,6 +57,22 @@ def _compile(unit, verbose):
     return out
 
 
+PROBE_PATH = os.path.join(HERE, "hbm_probe")
+
+
+def build_probe(verbose: bool = False) -> str:
+    """Compile the standalone HBM probe (csrc/hbm_probe.hip) to paper_2309_03912_amd/hbm_probe."""
+    cmd = [HIPCC, "--offload-arch=gfx950", "-std=c++20", "-O3", "-Xclang", "-target-feature", "-Xclang",
+           "-packed-fp32-ops", "-Wall", "-o", PROBE_PATH + ".tmp", os.path.join(CSRC, "hbm_probe.hip")]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    proc = subprocess.run(cmd, capture_output=True, text=True)
+    if proc.returncode != 0:
+        raise RuntimeError("hipcc failed on hbm_probe.hip:\n" + _filter(proc.stderr))
+    os.replace(PROBE_PATH + ".tmp", PROBE_PATH)
+    return PROBE_PATH
+
+
 def build(verbose: bool = False, jobs: int | None = None) -> str:
     """Compile every translation unit in parallel, link libhdc.so (always rebuilds)."""
     os.makedirs(BUILD_DIR, exist_ok=True)
@@ -74,3 +90,4 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
 
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_probe(verbose=True))

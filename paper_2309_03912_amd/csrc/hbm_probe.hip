@@ -1,0 +1,131 @@
+// HBM probe: the bandwidth this GPU actually delivers to plain streaming
+// kernels, as the denominator check for the library's roofline fractions.
+//
+// Read-only and copy kernels over 1 GiB of 16-byte vectors, each with the
+// default and the non-temporal cache policy, swept over block size and grid;
+// median of 7 timed launches (HIP events) per point.  Prints one line per
+// point and a JSON summary line.  Exit status 0 on success, 1 on a HIP error.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <vector>
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+#define CHECK(x)                                                               \
+  do {                                                                         \
+    hipError_t e_ = (x);                                                       \
+    if (e_ != hipSuccess) {                                                    \
+      std::printf("HIP error %s at line %d\n", hipGetErrorString(e_), __LINE__); \
+      return 1;                                                                \
+    }                                                                          \
+  } while (0)
+
+template <int U, bool kNT>
+__global__ __launch_bounds__(1024) void read_kernel(const u32x4* __restrict__ x, int64_t nvec, uint32_t* sink) {
+  uint32_t acc = 0;
+  const int64_t B = blockDim.x, stride = (int64_t)gridDim.x * B * U;
+  for (int64_t base = (int64_t)blockIdx.x * B * U + threadIdx.x; base < nvec; base += stride) {
+    u32x4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = base + u * B;
+      v[u] = i < nvec ? (kNT ? __builtin_nontemporal_load(x + i) : x[i]) : u32x4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+  }
+  if (acc == 0x9E3779B9u) sink[0] = acc;  // data-dependent store keeps the loads
+}
+
+template <int U, bool kNTLoad, bool kNTStore>
+__global__ __launch_bounds__(1024) void copy_kernel(const u32x4* __restrict__ x, u32x4* __restrict__ y,
+                                                    int64_t nvec) {
+  const int64_t B = blockDim.x, stride = (int64_t)gridDim.x * B * U;
+  for (int64_t base = (int64_t)blockIdx.x * B * U + threadIdx.x; base < nvec; base += stride) {
+    u32x4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = base + u * B;
+      if (i < nvec) v[u] = kNTLoad ? __builtin_nontemporal_load(x + i) : x[i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = base + u * B;
+      if (i < nvec) {
+        if (kNTStore)
+          __builtin_nontemporal_store(v[u], y + i);
+        else
+          y[i] = v[u];
+      }
+    }
+  }
+}
+
+template <class Launch>
+static int median_ms(Launch launch, float* out) {
+  hipEvent_t a, b;
+  CHECK(hipEventCreate(&a));
+  CHECK(hipEventCreate(&b));
+  launch();
+  CHECK(hipGetLastError());
+  CHECK(hipDeviceSynchronize());
+  std::vector<float> t;
+  for (int r = 0; r < 7; ++r) {
+    CHECK(hipEventRecord(a));
+    launch();
+    CHECK(hipEventRecord(b));
+    CHECK(hipEventSynchronize(b));
+    float ms = 0;
+    CHECK(hipEventElapsedTime(&ms, a, b));
+    t.push_back(ms);
+  }
+  std::sort(t.begin(), t.end());
+  *out = t[t.size() / 2];
+  CHECK(hipEventDestroy(a));
+  CHECK(hipEventDestroy(b));
+  return 0;
+}
+
+int main() {
+  const int64_t bytes = int64_t(1) << 30, nvec = bytes / 16;
+  u32x4 *x = nullptr, *y = nullptr;
+  uint32_t* sink = nullptr;
+  CHECK(hipMalloc(&x, bytes));
+  CHECK(hipMalloc(&y, bytes));
+  CHECK(hipMalloc(&sink, 64));
+  CHECK(hipMemset(x, 1, bytes));
+  CHECK(hipMemset(y, 0, bytes));
+  int cus = 0;
+  CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0));
+  const double gb = bytes / 1e6;  // GB/ms
+  double best[5] = {0, 0, 0, 0, 0};  // read, read-nt, copy, copy-nt-store, copy-nt-both
+  for (int block : {256, 512, 1024}) {
+    for (int gm : {2, 4, 8, 16, 32}) {
+      const unsigned g = (unsigned)(cus * gm);
+      float t[5];
+      if (median_ms([&] { read_kernel<8, false><<<g, block>>>(x, nvec, sink); }, &t[0])) return 1;
+      if (median_ms([&] { read_kernel<8, true><<<g, block>>>(x, nvec, sink); }, &t[1])) return 1;
+      if (median_ms([&] { copy_kernel<8, false, false><<<g, block>>>(x, y, nvec); }, &t[2])) return 1;
+      if (median_ms([&] { copy_kernel<8, false, true><<<g, block>>>(x, y, nvec); }, &t[3])) return 1;
+      if (median_ms([&] { copy_kernel<8, true, true><<<g, block>>>(x, y, nvec); }, &t[4])) return 1;
+      const double r[5] = {gb / t[0], gb / t[1], 2 * gb / t[2], 2 * gb / t[3], 2 * gb / t[4]};
+      for (int k = 0; k < 5; ++k) best[k] = std::max(best[k], r[k]);
+      std::printf("block %4d grid %5u  read %.0f  read-nt %.0f  copy %.0f  copy-nt-store %.0f  copy-nt %.0f GB/s\n",
+                  block, g, r[0], r[1], r[2], r[3], r[4]);
+      std::fflush(stdout);
+    }
+  }
+  float tm = 0;
+  if (median_ms([&] { (void)hipMemcpyAsync(y, x, bytes, hipMemcpyDeviceToDevice, 0); }, &tm)) return 1;
+  std::printf(
+      "{\"cus\": %d, \"best_read_GBps\": %.0f, \"best_read_nt_GBps\": %.0f, \"best_copy_GBps\": %.0f, "
+      "\"best_copy_nt_store_GBps\": %.0f, \"best_copy_nt_GBps\": %.0f, \"hipMemcpy_d2d_GBps\": %.0f}\n",
+      cus, best[0], best[1], best[2], best[3], best[4], 2 * gb / tm);
+  CHECK(hipFree(x));
+  CHECK(hipFree(y));
+  CHECK(hipFree(sink));
+  return 0;
+}
