@@ -32,7 +32,8 @@
  *  - Device faults are sticky and surface at the caller's next
  *    synchronisation (section 2.4, variant "no sensible implementation").
  *  - Calls from several host threads are safe.  Calls that share one
- *    workspace buffer must be ordered on one stream.
+ *    workspace buffer must be ordered on one stream.  A caller's workspace
+ *    must be 256-byte aligned (HDC_ERR_INVALID_ARGUMENT otherwise).
  */
 #ifndef HDC_H
 #define HDC_H
@@ -91,7 +92,10 @@ typedef enum hdc_op {
   HDC_OP_SEGMENTED_REDUCE = 2,
   HDC_OP_MAP_REDUCE = 3,
   HDC_OP_BATCH = 4,
-  HDC_OP_SCAN = 5
+  HDC_OP_SCAN = 5,
+  HDC_OP_DOT = 6 /* tuning class of transform_reduce with PRODUCT (dot products,
+                    two operands per element); its workspace is that of
+                    HDC_OP_TRANSFORM_REDUCE */
 } hdc_op;
 
 #define HDC_MAX_DEGREE 16
@@ -162,11 +166,21 @@ hdc_status hdc_map_reduce(const hdc_functor* f, const hdc_functor* g,
  * Prefix sums: y[i] = the fold of f over x[0..i] (exclusive = 1: over
  * x[0..i-1], so y[0] = 0).  acc PLAIN (y: float), COMPENSATED (y: double)
  * for F32/F16/BF16, EXACT_INT (y: int64, wrapping) for I32; IDENTITY,
- * AFFINE, HORNER.  Three stream-ordered passes (tile sums, tile offsets,
- * tile scans) with no waiting between blocks; results are bit-reproducible
- * for a fixed tuning.  x and y must not overlap.  Workspace:
- * hdc_workspace_size(HDC_OP_SCAN, dt, acc, n, 0, ...).  Bytes moved: x is
- * read twice, y written once.
+ * AFFINE, HORNER.  x and y must not overlap.  Workspace:
+ * hdc_workspace_size(HDC_OP_SCAN, dt, acc, n, 0, ...); calls sharing it must
+ * be ordered on one stream.  Two schedules, chosen by the tuning's `unroll`:
+ *  - any value but 1 (the default): one pass.  Tiles are handed out in
+ *    launch order.  Each tile publishes one node of a binary indexed tree
+ *    over the tile totals, and folds its carry from at most log2(tiles)
+ *    nodes of earlier tiles, in a fixed order.  The carry between tiles is
+ *    fp64 for floats and int64 for integers.  x is read once.  A small
+ *    clear kernel runs first on the same stream.  The 32-bit word at byte 4
+ *    of the workspace is nonzero after the call if a wait for an earlier
+ *    tile gave up; the output is then invalid.  Tiles start in order, so a
+ *    give-up is not expected.
+ *  - 1: three passes (tile sums, tile offsets, tile scans) with no waiting
+ *    between blocks.  x is read twice.
+ * Results are bit-reproducible for a fixed tuning.
  */
 hdc_status hdc_scan(const hdc_functor* f, hdc_dtype dt, const void* x,
                     void* y, int64_t n, hdc_accum acc, int32_t exclusive,
@@ -235,7 +249,9 @@ hdc_status hdc_validate_offsets(const int64_t* offsets, int64_t num_segments,
  * of the segmented pass (power of two, 1024..65536); small_seg: segments at
  * most this long are packed several per wavefront (0..1024); seg_per_wave:
  * how many small segments share one wavefront (power of two, 1..64, each
- * served by 64/seg_per_wave lanes).  Tuning changes
+ * served by 64/seg_per_wave lanes).  For HDC_OP_SCAN, block sets the tile
+ * (block * 16 elements) and unroll 1 selects the three-pass schedule.
+ * Tuning changes
  * the summation order, so the last bits of a floating-point sum may change;
  * results stay within the stated tolerance. */
 typedef struct hdc_tuning {

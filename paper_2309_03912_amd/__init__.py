@@ -29,7 +29,7 @@ OK, ERR_INVALID_ARGUMENT, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP = range(5)
 F32, F16, BF16, I32, I64, F64 = range(6)
 FN_IDENTITY, FN_AFFINE, FN_HORNER, FN_PRODUCT = range(4)
 ACC_PLAIN, ACC_COMPENSATED, ACC_EXACT_INT, ACC_EXACT = range(4)
-OP_MAP, OP_TRANSFORM_REDUCE, OP_SEGMENTED_REDUCE, OP_MAP_REDUCE, OP_BATCH, OP_SCAN = range(6)
+OP_MAP, OP_TRANSFORM_REDUCE, OP_SEGMENTED_REDUCE, OP_MAP_REDUCE, OP_BATCH, OP_SCAN, OP_DOT = range(7)
 MAX_DEGREE = 16
 
 DTYPE = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16, torch.int32: I32}

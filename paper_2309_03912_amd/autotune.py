@@ -32,7 +32,7 @@ import time
 import torch
 
 from . import (ACC_COMPENSATED, ACC_EXACT, ACC_EXACT_INT, ACC_PLAIN, BF16, F16, F32, I32, OP_BATCH, OP_MAP,
-               OP_MAP_REDUCE, OP_SCAN, OP_SEGMENTED_REDUCE, OP_TRANSFORM_REDUCE, get_tuning, set_tuning,
+               OP_DOT, OP_MAP_REDUCE, OP_SCAN, OP_SEGMENTED_REDUCE, OP_TRANSFORM_REDUCE, get_tuning, set_tuning,
                tuning_bucket)
 from . import map as hdc_map
 from . import batch_map_reduce, map_reduce, scan, segmented_reduce, transform_reduce, workspace
@@ -99,7 +99,7 @@ class Case:
             self.ws = workspace(dev, op, dt, acc, n)
             self.out = torch.empty((), dtype={ACC_PLAIN: torch.float32, ACC_COMPENSATED: torch.float64,
                                               ACC_EXACT_INT: torch.int64}[acc], device=dev)
-        if op == OP_TRANSFORM_REDUCE and dt != I32:
+        if op == OP_DOT:
             self.z = _inputs(dt, n, dev, seed=2)
 
     def run(self):
@@ -116,15 +116,14 @@ class Case:
         elif self.op == OP_TRANSFORM_REDUCE:
             fn = self.ident if self.dt == I32 else self.horner
             transform_reduce(self.x, fn, self.accname, out=self.out, ws=self.ws)
+        elif self.op == OP_DOT:
+            transform_reduce(self.x, {"fn": "product"}, self.accname, z=self.z, out=self.out, ws=self.ws)
         elif self.op == OP_MAP_REDUCE:
             fn = self.ident if self.dt == I32 else self.horner
             map_reduce(self.x, self.aff, fn, self.accname, out=self.y, result=self.out, ws=self.ws)
         else:
             fn = self.ident if self.dt == I32 else self.horner
             segmented_reduce(self.x, self.off, fn, self.accname, out=self.out, ws=self.ws)
-
-    def run_dot(self):
-        transform_reduce(self.x, {"fn": "product"}, self.accname, z=self.z, out=self.out, ws=self.ws)
 
     def output(self):
         if self.op == OP_BATCH:
@@ -171,8 +170,8 @@ def candidates(op, quick=False):
     base = [dict(block=b, unroll=u, grid_mult=g) for b, u, g in itertools.product(blocks, unrolls, gms)]
     if op == OP_BATCH:
         return base, [dict(chunk=c) for c in [8192, 16384, 32768, 65536]]
-    if op == OP_SCAN:
-        return [dict(block=b) for b in [256, 512, 1024]]
+    if op == OP_SCAN:  # tile size x schedule (unroll 1: three passes, else one pass)
+        return [dict(block=b, unroll=u) for b in [256, 512, 1024] for u in [1, 4]]
     if op != OP_SEGMENTED_REDUCE:
         return base
     seg = [dict(chunk=c, small_seg=s, seg_per_wave=w)
@@ -202,20 +201,14 @@ def tune_case(case: Case, quick=False, reps=5, rounds=3, log=print):
                         ref = out
                     elif not case.agrees(ref, out):
                         raise RuntimeError(f"candidate {trial[i]} disagrees with {trial[0]} on {case.key()}")
-                t = _time(case.run, reps)
-                if op == OP_TRANSFORM_REDUCE and dt != I32:
-                    t += _time(case.run_dot, reps)  # the class also serves dot products
-                times[i].append(t)
+                times[i].append(_time(case.run, reps))
         med = {i: statistics.median(v) for i, v in times.items()}
         top = sorted(med, key=med.get)[:3]
         re = {i: [] for i in top}
         for r in range(2 * rounds):
             for i in top:
                 set_tuning(op, dt, acc, b, **trial[i])
-                t = _time(case.run, reps)
-                if op == OP_TRANSFORM_REDUCE and dt != I32:
-                    t += _time(case.run_dot, reps)
-                re[i].append(t)
+                re[i].append(_time(case.run, reps))
         win = min(top, key=lambda i: statistics.median(re[i]))
         best = trial[win]
         set_tuning(op, dt, acc, b, **best)
@@ -237,6 +230,9 @@ def default_cases(dev, quick=False, log2n=28):
         Case(OP_TRANSFORM_REDUCE, BF16, ACC_COMPENSATED, n, dev),
         Case(OP_TRANSFORM_REDUCE, F16, ACC_COMPENSATED, n, dev),
         Case(OP_TRANSFORM_REDUCE, F32, ACC_COMPENSATED, n, dev),
+        Case(OP_DOT, F32, ACC_PLAIN, n, dev),
+        Case(OP_DOT, BF16, ACC_COMPENSATED, n, dev),
+        Case(OP_DOT, F16, ACC_COMPENSATED, n, dev),
     ]
     L = synth.segment_lengths(synth.seed_of(4))
     off = synth.offsets_from_lengths(L)
@@ -262,16 +258,36 @@ def write_cache(path, results):
         f.write("\n".join(lines) + "\n")
 
 
+def read_cache(path):
+    """The classes of an existing cache file, as write_cache writes them."""
+    results = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            v = [int(w) for w in line.split()]
+            results[tuple(v[:4])] = dict(zip(FIELDS, v[4:]))
+    return results
+
+
 def main(argv=None):
     p = argparse.ArgumentParser(description=__doc__)
     p.add_argument("--out", default=DEFAULT_CACHE)
     p.add_argument("--quick", action="store_true")
     p.add_argument("--log2n", type=int, default=28)
+    p.add_argument("--ops", default="", help="comma-separated op ids to tune (default: all)")
+    p.add_argument("--merge", default="", help="cache file whose other classes are kept in the output")
     a = p.parse_args(argv)
     dev = torch.device("cuda", 0)
     t0 = time.time()
-    results = {}
+    results = read_cache(a.merge) if a.merge else {}
+    ops = {int(o) for o in a.ops.split(",")} if a.ops else None
+    tuned = set()
     for case in default_cases(dev, a.quick, a.log2n):
+        # a class is tuned once, at the first (largest) size listed for it
+        if (ops is not None and case.op not in ops) or case.key() in tuned:
+            continue
+        tuned.add(case.key())
         results[case.key()] = tune_case(case, a.quick, log=lambda s: print(s, flush=True))
         del case
         torch.cuda.empty_cache()

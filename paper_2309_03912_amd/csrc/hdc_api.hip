@@ -71,7 +71,7 @@ namespace {
 // Tuning
 // ---------------------------------------------------------------------------
 
-constexpr int kOps = 6, kDtypes = 6, kAccs = 4, kBuckets = 4;
+constexpr int kOps = 7, kDtypes = 6, kAccs = 4, kBuckets = 4;
 std::mutex g_tune_mu;
 Tuning g_tune[kOps][kDtypes][kAccs][kBuckets];
 
@@ -166,6 +166,7 @@ std::vector<void*> g_ws_retired;
 // (device, stream), grown when needed and allowed.
 hdc_status resolve_workspace(void* ws, size_t ws_bytes, size_t need, hipStream_t stream, void** out) {
   if (ws) {
+    if ((uintptr_t)ws % 256 != 0) return fail(HDC_ERR_INVALID_ARGUMENT, "workspace is not 256-byte aligned");
     if (ws_bytes < need)
       return fail(HDC_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes needed", ws_bytes,
                   need);
@@ -299,7 +300,8 @@ static hdc_status reduce_common(const hdc_functor* f, const hdc_functor* fm, hdc
   hipStream_t st = (hipStream_t)stream;
   void* ws = nullptr;
   HDC_TRY(resolve_workspace(workspace, ws_bytes, reduce_workspace_bytes(), st, &ws));
-  const Tuning t = tuning_for(fused ? HDC_OP_MAP_REDUCE : HDC_OP_TRANSFORM_REDUCE, dt, acc, n);
+  const int op = fused ? HDC_OP_MAP_REDUCE : f->id == HDC_FN_PRODUCT ? HDC_OP_DOT : HDC_OP_TRANSFORM_REDUCE;
+  const Tuning t = tuning_for(op, dt, acc, n);
 
   if (!fused) return run_reduce(*f, dt, x, z, n, acc, out, ws, t, st);
   switch (dt) {
@@ -467,6 +469,7 @@ hdc_status hdc_workspace_size(int op, hdc_dtype dt, hdc_accum acc, int64_t n, in
   switch (op) {
     case HDC_OP_MAP: *bytes = 0; return HDC_OK;
     case HDC_OP_TRANSFORM_REDUCE:
+    case HDC_OP_DOT:
     case HDC_OP_MAP_REDUCE: *bytes = reduce_workspace_bytes(); return HDC_OK;
     case HDC_OP_SCAN:
       *bytes = scan_workspace_bytes(n);

@@ -174,6 +174,11 @@ hdc_status launch_batch(const FM& fm, const F& f, const hdc_batch_call* calls, c
   return check_launch("batch combine launch");
 }
 
+// Scan: t.unroll == 1 selects the three-pass schedule, any other value the
+// single pass.  Workspace (scan_workspace_bytes):
+//   three passes: tile sums | tile offsets, one fold state per tile each;
+//   single pass:  256-byte header (ticket, status) | 2 words per tile (the
+//                 tile's tree node).
 template <class F, class S, class Acc>
 hdc_status launch_scan(const F& f, const void* x, void* y, int64_t n, int exclusive, void* ws, const Tuning& t,
                        hipStream_t st) {
@@ -181,30 +186,45 @@ hdc_status launch_scan(const F& f, const void* x, void* y, int64_t n, int exclus
   using OutT = typename ScanOut<Acc>::T;
   const int64_t tile = (int64_t)t.block * kScanE;
   const int64_t G = (n + tile - 1) / tile;
-  Acc* sums = static_cast<Acc*>(ws);
-  Acc* offsets = reinterpret_cast<Acc*>(static_cast<char*>(ws) + round_up((size_t)G * sizeof(Acc), 256));
+  if (G * t.block > (int64_t)UINT32_MAX) return fail(HDC_ERR_UNSUPPORTED, "n = %lld is too large for one scan", (long long)n);
   const bool xa = (uintptr_t)x % 16 == 0, ya = (uintptr_t)y % 16 == 0;
   const T* xp = static_cast<const T*>(x);
   OutT* yp = static_cast<OutT*>(y);
+  const dim3 grid((unsigned)G), block(t.block);
+  if (t.unroll != 1) {
+    uint64_t* w = static_cast<uint64_t*>(ws);
+    const int64_t nwords = 32 + 2 * G;
+    const ScanLB lb{static_cast<uint32_t*>(ws), static_cast<uint32_t*>(ws) + 1, w + 32};
+    const int64_t cb = (nwords + 255) / 256;
+    scan_lb_clear_kernel<<<dim3((unsigned)(cb < 1024 ? cb : 1024)), dim3(256), 0, st>>>(w, nwords);
+    HDC_TRY(check_launch("scan look-back clear launch"));
+    if (xa && ya)
+      scan_onepass_kernel<F, S, Acc, true, true><<<grid, block, 0, st>>>(f, xp, n, lb, yp, exclusive);
+    else if (xa)
+      scan_onepass_kernel<F, S, Acc, true, false><<<grid, block, 0, st>>>(f, xp, n, lb, yp, exclusive);
+    else if (ya)
+      scan_onepass_kernel<F, S, Acc, false, true><<<grid, block, 0, st>>>(f, xp, n, lb, yp, exclusive);
+    else
+      scan_onepass_kernel<F, S, Acc, false, false><<<grid, block, 0, st>>>(f, xp, n, lb, yp, exclusive);
+    return check_launch("scan single-pass launch");
+  }
+  Acc* sums = static_cast<Acc*>(ws);
+  Acc* offsets = reinterpret_cast<Acc*>(static_cast<char*>(ws) + round_up((size_t)G * sizeof(Acc), 256));
   if (xa)
-    scan_tile_sums_kernel<F, S, Acc, true><<<dim3((unsigned)G), dim3(t.block), 0, st>>>(f, xp, n, sums);
+    scan_tile_sums_kernel<F, S, Acc, true><<<grid, block, 0, st>>>(f, xp, n, sums);
   else
-    scan_tile_sums_kernel<F, S, Acc, false><<<dim3((unsigned)G), dim3(t.block), 0, st>>>(f, xp, n, sums);
+    scan_tile_sums_kernel<F, S, Acc, false><<<grid, block, 0, st>>>(f, xp, n, sums);
   HDC_TRY(check_launch("scan tile-sum launch"));
   scan_offsets_kernel<Acc><<<dim3(1), dim3(1024), 0, st>>>(sums, G, offsets);
   HDC_TRY(check_launch("scan offset launch"));
   if (xa && ya)
-    scan_tiles_kernel<F, S, Acc, true, true><<<dim3((unsigned)G), dim3(t.block), 0, st>>>(f, xp, n, offsets, yp,
-                                                                                         exclusive);
+    scan_tiles_kernel<F, S, Acc, true, true><<<grid, block, 0, st>>>(f, xp, n, offsets, yp, exclusive);
   else if (xa)
-    scan_tiles_kernel<F, S, Acc, true, false><<<dim3((unsigned)G), dim3(t.block), 0, st>>>(f, xp, n, offsets, yp,
-                                                                                          exclusive);
+    scan_tiles_kernel<F, S, Acc, true, false><<<grid, block, 0, st>>>(f, xp, n, offsets, yp, exclusive);
   else if (ya)
-    scan_tiles_kernel<F, S, Acc, false, true><<<dim3((unsigned)G), dim3(t.block), 0, st>>>(f, xp, n, offsets, yp,
-                                                                                          exclusive);
+    scan_tiles_kernel<F, S, Acc, false, true><<<grid, block, 0, st>>>(f, xp, n, offsets, yp, exclusive);
   else
-    scan_tiles_kernel<F, S, Acc, false, false><<<dim3((unsigned)G), dim3(t.block), 0, st>>>(f, xp, n, offsets, yp,
-                                                                                           exclusive);
+    scan_tiles_kernel<F, S, Acc, false, false><<<grid, block, 0, st>>>(f, xp, n, offsets, yp, exclusive);
   return check_launch("scan tile launch");
 }
 

@@ -221,7 +221,6 @@ __global__ __launch_bounds__(1024) void seg_items_kernel(F f, const elem_t<S>* _
   const int64_t npart = cp < p.cap_part ? cp : p.cap_part;
   const int64_t npieces = nfull + npart;
   const int64_t ngroups = (S_ + p.spw - 1) / p.spw;
-  const int64_t nitems = npieces + ngroups;
   Acc* partials = static_cast<Acc*>(p.partials);
   auto piece_at = [&](int64_t i) -> SegPiece { return i < nfull ? p.full_list[i] : p.part_list[i - nfull]; };
   auto valid = [&](const SegPiece& pc) { return pc.seg >= 0 && pc.seg < S_; };

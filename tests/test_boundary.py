@@ -93,6 +93,8 @@ def test_transform_reduce_rejects_bad_arguments():
                                         f=fn({"fn": "horner", "coef": [1.0]}))) == hdc.ERR_UNSUPPORTED
     assert L.hdc_transform_reduce(*args(wsb=need - 1)) == hdc.ERR_WORKSPACE
     assert "smaller" in last()
+    assert L.hdc_transform_reduce(*args(ws=FAKE + 8)) == hdc.ERR_INVALID_ARGUMENT
+    assert "256-byte aligned" in last()
 
 
 def test_map_reduce_and_segmented_reject_bad_arguments():
@@ -117,6 +119,7 @@ def test_map_reduce_and_segmented_reject_bad_arguments():
 def test_workspace_sizes():
     assert hdc.workspace_size(hdc.OP_MAP, hdc.F32, 0, 1 << 20) == 0
     a = hdc.workspace_size(hdc.OP_TRANSFORM_REDUCE, hdc.F32, 0, 1 << 28)
+    assert hdc.workspace_size(hdc.OP_DOT, hdc.F32, 0, 1 << 28) == a
     assert 0 < a <= 1 << 22
     with pytest.raises(hdc.HdcError):
         hdc.workspace_size(99, hdc.F32, 0, 10)
@@ -131,6 +134,12 @@ def test_tuning_roundtrip_and_cache(tmp_path):
         assert t["block"] == 512 and t["unroll"] == 2
     hdc.set_tuning(hdc.OP_MAP, hdc.F16, hdc.ACC_PLAIN, 1, block=128)
     assert hdc.get_tuning(hdc.OP_MAP, hdc.F16, hdc.ACC_PLAIN, 1)["block"] == 128
+    before = hdc.get_tuning(hdc.OP_TRANSFORM_REDUCE, hdc.F32, hdc.ACC_PLAIN, 3)
+    dot = hdc.get_tuning(hdc.OP_DOT, hdc.F32, hdc.ACC_PLAIN, 3)
+    hdc.set_tuning(hdc.OP_DOT, hdc.F32, hdc.ACC_PLAIN, 3, block=64 if dot["block"] != 64 else 128)
+    assert hdc.get_tuning(hdc.OP_DOT, hdc.F32, hdc.ACC_PLAIN, 3)["block"] != dot["block"]
+    assert hdc.get_tuning(hdc.OP_TRANSFORM_REDUCE, hdc.F32, hdc.ACC_PLAIN, 3) == before  # its own class
+    hdc.set_tuning(hdc.OP_DOT, hdc.F32, hdc.ACC_PLAIN, 3, **dot)
     assert hdc.get_tuning(hdc.OP_MAP, hdc.F16, hdc.ACC_PLAIN, 2)["block"] == 512
     assert [hdc.tuning_bucket(n) for n in (0, 65535, 65536, 1 << 20, (1 << 24) - 1, 1 << 28)] == [0, 0, 1, 2, 2, 3]
     with pytest.raises(hdc.HdcError):

@@ -1,7 +1,9 @@
 """GPU parity of hdc_scan (prefix sums) against the oracle, through the C ABI.
 
 Per element: integers bit-exact; floating point within 1e-6 of the running
-sum of magnitudes of the exact prefix sum (exactly 0 where it is 0)."""
+sum of magnitudes of the exact prefix sum (exactly 0 where it is 0).  Every
+test runs under both schedules: the single pass with a decoupled look-back
+(tuning unroll != 1, the default) and the three-pass schedule (unroll 1)."""
 import numpy as np
 import pytest
 import torch
@@ -17,8 +19,33 @@ FNS = {"identity": {"fn": "identity"}, "affine": {"fn": "affine", "a": 2.5, "b":
 SIZES = [0, 1, 15, 16, 17, 4095, 4096, 4097, 16383, 16384, 16385, 100003, (1 << 18) + 7]
 
 
+SCAN_CLASSES = [(hdc.F32, hdc.ACC_PLAIN), (hdc.F32, hdc.ACC_COMPENSATED), (hdc.F16, hdc.ACC_PLAIN),
+                (hdc.F16, hdc.ACC_COMPENSATED), (hdc.BF16, hdc.ACC_PLAIN), (hdc.BF16, hdc.ACC_COMPENSATED),
+                (hdc.I32, hdc.ACC_EXACT_INT)]
+
+
 def gpu():
     return torch.device("cuda", 0)
+
+
+def set_scan_tuning(unroll, block=0):
+    for dt, acc in SCAN_CLASSES:
+        hdc.set_tuning(hdc.OP_SCAN, dt, acc, -1, block=block, unroll=unroll)
+
+
+@pytest.fixture(params=["single_pass", "three_pass"], autouse=True)
+def schedule(request):
+    saved = {(dt, acc, b): hdc.get_tuning(hdc.OP_SCAN, dt, acc, b) for dt, acc in SCAN_CLASSES for b in range(4)}
+    set_scan_tuning(4 if request.param == "single_pass" else 1)
+    yield request.param
+    for (dt, acc, b), t in saved.items():
+        hdc.set_tuning(hdc.OP_SCAN, dt, acc, b, **t)
+
+
+def lookback_status(ws):
+    """The single pass's status word (byte 4 of the workspace): nonzero if a look-back gave up."""
+    torch.cuda.synchronize()
+    return int(ws[4:8].cpu().view(torch.int32).item())
 
 
 def check(got, ref, what):
@@ -70,3 +97,43 @@ def test_scan_large_sampled():
     for k in (0, 12345, 1 << 20, n // 2 + 17, n - 1):
         r = oracle.reduce(FNS["horner"], x[:k + 1])
         assert abs(y[k] - r["exact"]) <= 1e-6 * r["abs_sum"], k
+
+
+@pytest.mark.parametrize("block", [64, 256, 1024])
+def test_scan_many_tiles_and_status(block, schedule):
+    """Thousands of tiles (the look-back crosses windows of 64 predecessors), every output checked."""
+    set_scan_tuning(4 if schedule == "single_pass" else 1, block=block)
+    n = 64 * 16 * 3000 + 123 if block == 64 else (1 << 22) + 5
+    x = synth.uniform_pm1_f32(11, 0, n)
+    ws = hdc.workspace(gpu(), hdc.OP_SCAN, hdc.F32, hdc.ACC_COMPENSATED, n)
+    y = hdc.scan(x.to(gpu()), FNS["horner"], "compensated", ws=ws)
+    if schedule == "single_pass":
+        assert lookback_status(ws) == 0
+    ref = oracle.scan(FNS["horner"], x)
+    check(y, ref, f"block {block}")
+    y2 = hdc.scan(x.to(gpu()), FNS["horner"], "compensated", ws=ws)
+    assert torch.equal(y, y2)
+    xi = synth.uniform_int(12, 10, n)
+    wsi = hdc.workspace(gpu(), hdc.OP_SCAN, hdc.I32, hdc.ACC_EXACT_INT, n)
+    yi = hdc.scan(xi.to(gpu()), {"fn": "affine", "a": 3, "b": -7}, "exact_int", exclusive=True, ws=wsi)
+    if schedule == "single_pass":
+        assert lookback_status(wsi) == 0
+    assert np.array_equal(yi.cpu().numpy(), oracle.scan({"fn": "affine", "a": 3, "b": -7}, xi, True)["isum"])
+
+
+def test_scan_full_size_sampled(schedule):
+    """2^28 f32 Horner scan in the launch configuration the benchmark times: sampled prefixes vs the oracle,
+    and the last output vs the oracle's full reduction."""
+    n = 1 << 28
+    x = synth.uniform_pm1_f32(synth.seed_of(2), synth.STREAM["x"], n, gpu())
+    ws = hdc.workspace(gpu(), hdc.OP_SCAN, hdc.F32, hdc.ACC_PLAIN, n)
+    y = hdc.scan(x, FNS["horner"], "plain", ws=ws)
+    if schedule == "single_pass":
+        assert lookback_status(ws) == 0
+    xc = x.cpu()
+    for k in (0, 16383, 16384, 1 << 24, (1 << 27) + 12345, n - 1):
+        r = oracle.reduce(FNS["horner"], xc[:k + 1])
+        got = y[k].item()
+        assert abs(got - r["exact"]) <= 1e-6 * r["abs_sum"], (k, got, r["exact"])
+    del x, y
+    torch.cuda.empty_cache()
