@@ -65,14 +65,71 @@ __host__ __device__ __forceinline__ void fold_elem(Acc& a, const F& f, elem_t<S>
 template <class F, int N>
 __host__ __device__ __forceinline__ void eval_batch(const F& f, float (&t)[N]) {
   if constexpr (std::is_same_v<F, Horner>) {
+    // Every coefficient index is a constant in both forms below, so the
+    // coefficients stay in scalar registers instead of being fetched once
+    // per step.  Large batches unroll over the largest degree with a uniform
+    // guard per step; small batches (where the guards' saved conditions would
+    // crowd the scalar registers) enter a straight chain at their degree.
     float acc[N];
-    const float top = f.c[f.degree];
+    if constexpr (N >= 8) {
+      float top = f.c[0];
 #pragma unroll
-    for (int i = 0; i < N; ++i) acc[i] = top;
-    for (int k = f.degree - 1; k >= 0; --k) {
-      const float ck = f.c[k];
+      for (int k = 1; k <= kMaxDegree; ++k) top = k == f.degree ? f.c[k] : top;
 #pragma unroll
-      for (int i = 0; i < N; ++i) acc[i] = __builtin_fmaf(acc[i], t[i], ck);
+      for (int i = 0; i < N; ++i) acc[i] = top;
+#pragma unroll
+      for (int k = kMaxDegree - 1; k >= 0; --k) {
+        if (k < f.degree) {
+          const float ck = f.c[k];
+#pragma unroll
+          for (int i = 0; i < N; ++i) acc[i] = __builtin_fmaf(acc[i], t[i], ck);
+        }
+      }
+    } else {
+      auto start = [&](int d) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc[i] = f.c[d];
+      };
+      auto step = [&](int k) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc[i] = __builtin_fmaf(acc[i], t[i], f.c[k]);
+      };
+      switch (f.degree) {
+        case 16: start(16); goto s15;
+        case 15: start(15); goto s14;
+        case 14: start(14); goto s13;
+        case 13: start(13); goto s12;
+        case 12: start(12); goto s11;
+        case 11: start(11); goto s10;
+        case 10: start(10); goto s9;
+        case 9: start(9); goto s8;
+        case 8: start(8); goto s7;
+        case 7: start(7); goto s6;
+        case 6: start(6); goto s5;
+        case 5: start(5); goto s4;
+        case 4: start(4); goto s3;
+        case 3: start(3); goto s2;
+        case 2: start(2); goto s1;
+        case 1: start(1); goto s0;
+        default: start(0); goto done;
+      }
+    s15: step(15);
+    s14: step(14);
+    s13: step(13);
+    s12: step(12);
+    s11: step(11);
+    s10: step(10);
+    s9: step(9);
+    s8: step(8);
+    s7: step(7);
+    s6: step(6);
+    s5: step(5);
+    s4: step(4);
+    s3: step(3);
+    s2: step(2);
+    s1: step(1);
+    s0: step(0);
+    done:;
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) t[i] = acc[i];

@@ -324,3 +324,28 @@ def test_exact_fp16_nonfinite_and_fused():
     y, r = hdc.map_reduce(x.to(gpu()), FNS["affine"], {"fn": "identity"}, "exact")
     assert torch.equal(bits(y.cpu()), bits(oracle.map(FNS["affine"], x)))
     assert r.item() == oracle.reduce({"fn": "identity"}, x)["exact"]
+
+
+def horner_of_degree(d, seed=0):
+    """Degree-d coefficients with mixed signs and magnitudes (exact in fp32); degree 3 gets a -0.0 top."""
+    g = torch.Generator().manual_seed(1000 + d + seed)
+    c = ((torch.randint(-64, 65, (d + 1,), generator=g).double()) / 32.0).tolist()
+    if d == 3:
+        c[-1] = -0.0
+    return {"fn": "horner", "coef": c}
+
+
+@pytest.mark.parametrize("degree", range(hdc.MAX_DEGREE + 1))
+def test_horner_every_degree(degree):
+    """Every Horner degree through every batch form of the kernels: maps bit-exact, sums within tolerance."""
+    fn = horner_of_degree(degree)
+    for n in (4097, (1 << 16) + 3):
+        x = make_x(n, torch.float32, seed=degree + 1)
+        y = hdc.map(x.to(gpu()), fn)
+        assert torch.equal(bits(y.cpu()), bits(oracle.map(fn, x))), (degree, n)
+        ref = oracle.reduce(fn, x)
+        for acc in ("plain", "compensated"):
+            assert_close_sum(hdc.transform_reduce(x.to(gpu()), fn, acc).item(), ref, f"d={degree} {acc} n={n}")
+        x16 = make_x(n, torch.float16, seed=degree + 2)
+        y16 = hdc.map(x16.to(gpu()), fn)
+        assert torch.equal(bits(y16.cpu()), bits(oracle.map(fn, x16))), (degree, n, "f16")

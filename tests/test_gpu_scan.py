@@ -137,3 +137,12 @@ def test_scan_full_size_sampled(schedule):
         assert abs(got - r["exact"]) <= 1e-6 * r["abs_sum"], (k, got, r["exact"])
     del x, y
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("degree", [0, 1, 7, 16])
+def test_scan_horner_degrees(degree, schedule):
+    g = torch.Generator().manual_seed(3000 + degree)
+    fn = {"fn": "horner", "coef": (torch.randint(-64, 65, (degree + 1,), generator=g).double() / 32.0).tolist()}
+    x = synth.uniform_pm1_f32(degree + 30, 0, 70001)
+    y = hdc.scan(x.to(gpu()), fn, "compensated")
+    check(y, oracle.scan(fn, x), f"degree {degree}")

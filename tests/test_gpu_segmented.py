@@ -30,8 +30,9 @@ def gpu():
 
 
 def edge_lengths(seed=0, count=600):
-    """Lengths that straddle every class boundary of the default tuning
-    (small <= 128 packed, pieces of 4096) plus random ones."""
+    """Lengths that straddle the small-segment and piece boundaries of the
+    tunings (64 .. 1024, pieces of 1024 .. 65536), empty segments, plus
+    random ones."""
     rng = np.random.default_rng(seed)
     special = [0, 0, 1, 2, 7, 8, 9, 63, 64, 65, 127, 128, 129, 130, 1000, 4095, 4096, 4097, 8191, 8192, 8193,
                3 * 4096, 3 * 4096 + 5, 20000, 0, 1, 70000]
@@ -140,3 +141,16 @@ def test_segmented_full_lognormal_workload(acc):
     r = hdc.segmented_reduce(xg, off.to(gpu()), FNS["horner"], acc)
     torch.cuda.synchronize()
     check_segments(r, oracle.segmented(FNS["horner"], xg.cpu(), off), f"lognormal {acc}")
+
+
+@pytest.mark.parametrize("degree", [0, 1, 2, 3, 7, 8, 9, 15, 16])
+def test_segmented_horner_degrees(degree):
+    """Horner of several degrees through the segmented passes (pieces and packed small segments)."""
+    g = torch.Generator().manual_seed(2000 + degree)
+    fn = {"fn": "horner", "coef": (torch.randint(-64, 65, (degree + 1,), generator=g).double() / 32.0).tolist()}
+    L = edge_lengths(seed=degree, count=200)
+    off = synth.offsets_from_lengths(L)
+    x = synth.uniform_pm1_f32(degree + 20, 0, int(off[-1]))
+    for acc in ("plain", "compensated"):
+        r = hdc.segmented_reduce(x.to(gpu()), off.to(gpu()), fn, acc)
+        check_segments(r, oracle.segmented(fn, x, off), f"degree {degree} {acc}")

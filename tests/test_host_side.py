@@ -31,6 +31,19 @@ def test_host_map_bit_exact(dt):
                 assert torch.equal(bits(y), bits(oracle.map(fn, x))), (fn["fn"], n, threads)
 
 
+def test_host_horner_every_degree():
+    """Every Horner degree (the batch evaluation enters its fma chain at the degree) against the oracle."""
+    for d in range(hdc.MAX_DEGREE + 1):
+        g = torch.Generator().manual_seed(1000 + d)
+        c = (torch.randint(-64, 65, (d + 1,), generator=g).double() / 32.0).tolist()
+        if d == 3:
+            c[-1] = -0.0
+        fn = {"fn": "horner", "coef": c}
+        for dt in (torch.float32, torch.float16):
+            x = synth.to_storage(synth.uniform_pm1_f32(d + 1, 0, 4099).double(), dt)
+            assert torch.equal(bits(hdc.host_map(x, fn)), bits(oracle.map(fn, x))), (d, dt)
+
+
 def test_host_map_16bit_all_patterns():
     for dt in (torch.float16, torch.bfloat16):
         x = torch.arange(-32768, 32768, dtype=torch.int32).to(torch.int16).view(dt)
