@@ -40,7 +40,7 @@ def parse():
     p.add_argument("--no-check", action="store_true", help="skip the oracle accuracy checks")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-forms", action="store_true", help="only the headline plain-FP32 step")
-    p.add_argument("--forms", default="c3,c4,c5,scan")
+    p.add_argument("--forms", default="c3,c4,c5,scan,host")
     p.add_argument("--cpu-sample-log2", type=int, default=28)
     p.add_argument("--with-copy", action="store_true",
                    help="add a plain copy (identity map, f32) to each step: the reference kernel of known size "
@@ -517,6 +517,32 @@ def form_scan(args, torch, hdc, synth):
     return res
 
 
+def form_host(args, torch, hdc, synth):
+    """The same callables on the host side (hdc_host_* on CPU tensors), on every core of the process:
+    the step's map and Horner sum over a 2^26-element sample, against the GPU's per-op rate."""
+    import oracle
+    m = 1 << 26
+    x = synth.uniform_pm1_f32(synth.seed_of(2), synth.STREAM["x"], m)
+    hor = hdc.horner(synth.horner_coefficients(8))
+    aff = hdc.affine(2.5, 0.5)
+    threads = host_cores()
+    y = torch.empty_like(x)
+    hdc.host_map(x, aff, out=y, threads=threads)  # warm (pages touched)
+    t0 = time.perf_counter()
+    hdc.host_map(x, aff, out=y, threads=threads)
+    t_map = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    r = hdc.host_transform_reduce(x, hor, "plain", threads=threads)
+    t_sum = time.perf_counter() - t0
+    ref = oracle.reduce(hor, x)
+    res = {"n": m, "threads": threads,
+           "map_f32_affine_GBps": round(8 * m / t_map / 1e9, 2),
+           "sum_f32_horner_GBps": round(4 * m / t_sum / 1e9, 2),
+           "sum_err_over_abs_sum": abs(float(r) - ref["exact"]) / ref["abs_sum"],
+           "map_bit_exact": bool(torch.equal(y.view(torch.int32), oracle.map(aff, x).view(torch.int32)))}
+    return res
+
+
 def measured_traffic(op_name):
     """HBM bytes per launch of `op_name` from the committed counter summary, or None when the kernel
     sources changed since the counters were taken (or the op was not measured)."""
@@ -591,6 +617,8 @@ def main():
             forms["graph_64_calls"] = form_graph(args, torch, hdc, synth)
         if "scan" in want:
             forms["scan"] = form_scan(args, torch, hdc, synth)
+        if "host" in want:
+            forms["host_side"] = form_host(args, torch, hdc, synth)
         out["forms"] = forms
     print(json.dumps(out), flush=True)
 

@@ -16,10 +16,21 @@
 
 namespace hdc {
 
+// Elements per batch of the host loops: the batch evaluation (one
+// coefficient at a time over the batch) is what the host compiler vectorizes.
+constexpr int kHostBatch = 16;
+
 template <class F, class S>
   requires host_callable<F>
 void host_map_range(const F& f, const elem_t<S>* x, elem_t<S>* y, int64_t lo, int64_t hi) {
-  for (int64_t i = lo; i < hi; ++i) y[i] = map_elem<F, S>(f, x[i]);
+  int64_t i = lo;
+  for (; i + kHostBatch <= hi; i += kHostBatch) {
+    elem_t<S> in[kHostBatch], out[kHostBatch];
+    for (int k = 0; k < kHostBatch; ++k) in[k] = x[i + k];
+    map_batch<F, S>(f, in, out);
+    for (int k = 0; k < kHostBatch; ++k) y[i + k] = out[k];
+  }
+  for (; i < hi; ++i) y[i] = map_elem<F, S>(f, x[i]);
 }
 
 // Blocked fold of [lo, hi): blocks of kHostBlock elements into four
@@ -34,7 +45,16 @@ Acc host_fold_range(const F& f, const elem_t<S>* x, const elem_t<S>* z, int64_t 
   for (int64_t b = lo; b < hi; b += kHostBlock) {
     const int64_t e = hi < b + kHostBlock ? hi : b + kHostBlock;
     Acc part[4] = {Acc::zero(), Acc::zero(), Acc::zero(), Acc::zero()};
-    for (int64_t i = b; i < e; ++i) fold_elem<F, S>(part[(i - b) & 3], f, x[i], F::binary ? z[i] : x[i]);
+    int64_t i = b;
+    if constexpr (!std::is_same_v<S, I32> && !F::binary) {
+      for (; i + kHostBatch <= e; i += kHostBatch) {  // the same terms as fold_elem, a batch at a time
+        float t[kHostBatch];
+        for (int k = 0; k < kHostBatch; ++k) t[k] = S::widen(x[i + k]);
+        eval_batch(f, t);
+        for (int k = 0; k < kHostBatch; ++k) part[(i - b + k) & 3].add(t[k]);
+      }
+    }
+    for (; i < e; ++i) fold_elem<F, S>(part[(i - b) & 3], f, x[i], F::binary ? z[i] : x[i]);
     total = Acc::merge(total, Acc::merge(Acc::merge(part[0], part[1]), Acc::merge(part[2], part[3])));
   }
   return total;

@@ -142,7 +142,7 @@ __host__ __device__ __forceinline__ void eval_batch(const F& f, float (&t)[N]) {
 // Map a batch of storage values: widen, evaluate, narrow (bit copy for
 // Identity, integer map for int32 storage).
 template <class F, class S, int N>
-__device__ __forceinline__ void map_batch(const F& f, const elem_t<S> (&in)[N], elem_t<S> (&out)[N]) {
+__host__ __device__ __forceinline__ void map_batch(const F& f, const elem_t<S> (&in)[N], elem_t<S> (&out)[N]) {
   if constexpr (std::is_same_v<S, I32> || std::is_same_v<F, Identity>) {
 #pragma unroll
     for (int i = 0; i < N; ++i) out[i] = map_elem<F, S>(f, in[i]);
