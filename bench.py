@@ -497,7 +497,8 @@ def form_graph(args, torch, hdc, synth):
 
 
 def form_scan(args, torch, hdc, synth):
-    """Prefix sums (inclusive) of p(x) over n f32 values: x is read twice, y written once."""
+    """Prefix sums (inclusive) of p(x) over n f32 values and over the lognormal segments; GB/s of the
+    algorithmic bytes (x read once, y written once)."""
     dev = torch.device("cuda", 0)
     n = 1 << args.log2n
     x = synth.uniform_pm1_f32(synth.seed_of(2), synth.STREAM["x"], n, dev)
@@ -509,10 +510,24 @@ def form_scan(args, torch, hdc, synth):
     yi = torch.empty(n, dtype=torch.int64, device=dev)
     wsi = hdc.workspace(dev, hdc.OP_SCAN, hdc.I32, hdc.ACC_EXACT_INT, n)
     ti = ev_time(torch, lambda: hdc.scan(xi, hdc.identity(), "exact_int", out=yi, ws=wsi))
-    res = {"n": n, "f32_horner_ms": round(t, 5), "f32_horner_GBps": round(gbps(12 * n, t), 1),
-           "i32_to_i64_ms": round(ti, 5), "i32_to_i64_GBps": round(gbps(16 * n, ti), 1),
-           "bytes_per_element": "f32: 4+4 read + 4 write; i32->i64: 4+4 read + 8 write"}
+    res = {"n": n, "f32_horner_ms": round(t, 5), "f32_horner_GBps": round(gbps(8 * n, t), 1),
+           "i32_to_i64_ms": round(ti, 5), "i32_to_i64_GBps": round(gbps(12 * n, ti), 1),
+           "bytes_per_element": "algorithmic: f32 4 read + 4 write; i32->i64 4 read + 8 write"}
     del x, y, xi, yi
+    torch.cuda.empty_cache()
+    # segmented scan over the segmented form's 100,000 lognormal segments
+    seed = synth.seed_of(4)
+    L = synth.segment_lengths(seed)
+    off = synth.offsets_from_lengths(L)
+    m = int(off[-1])
+    xs = synth.uniform_pm1_f32(seed, synth.STREAM["x"], m, dev)
+    ys = torch.empty(m, dtype=torch.float32, device=dev)
+    offg = off.to(dev)
+    wss = hdc.workspace(dev, hdc.OP_SCAN, hdc.F32, hdc.ACC_PLAIN, m)
+    ts = ev_time(torch, lambda: hdc.segmented_scan(xs, offg, hor, "plain", out=ys, ws=wss))
+    res["segmented_100k_lognormal"] = {"elements": m, "segments": int(L.numel()), "f32_horner_ms": round(ts, 5),
+                                       "GBps": round(gbps(8 * m + 8 * (L.numel() + 1), ts), 1)}
+    del xs, ys
     torch.cuda.empty_cache()
     return res
 

@@ -186,6 +186,27 @@ hdc_status hdc_scan(const hdc_functor* f, hdc_dtype dt, const void* x,
                     void* y, int64_t n, hdc_accum acc, int32_t exclusive,
                     void* workspace, size_t ws_bytes, void* stream);
 
+/*
+ * Segmented prefix sums: for every segment j and every i in
+ * [offsets[j], offsets[j+1]), y[i] = the fold of f over x[offsets[j]..i]
+ * (exclusive = 1: over x[offsets[j]..i-1], so a segment's first output is 0).
+ * The prefix restarts at every segment start.  x and y hold `total` elements.
+ * offsets is a DEVICE array of num_segments + 1 non-decreasing entries with
+ * offsets[num_segments] <= total; this is a precondition and is not checked.
+ * Only positions inside a segment are written.  dtype, functor and
+ * accumulation as hdc_scan; tuning class HDC_OP_SCAN.  One pass or three, as
+ * hdc_scan; every wavefront finds the segment starts in its part of a tile
+ * from the offsets (a 64-way search, then the next 64 boundaries at a time).
+ * Bytes moved: as hdc_scan, plus the offsets once.  Workspace:
+ * hdc_workspace_size(HDC_OP_SCAN, dt, acc, total, 0, ...).
+ * num_segments == 0 or total == 0 writes nothing.
+ */
+hdc_status hdc_segmented_scan(const hdc_functor* f, hdc_dtype dt, const void* x,
+                              const int64_t* offsets, int64_t num_segments,
+                              int64_t total, void* y, hdc_accum acc,
+                              int32_t exclusive, void* workspace,
+                              size_t ws_bytes, void* stream);
+
 /* One call of a grouped batch (device pointers). */
 typedef struct hdc_batch_call {
   const void* x;

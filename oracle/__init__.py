@@ -180,6 +180,37 @@ def scan(spec: dict, x: torch.Tensor, exclusive: bool = False) -> dict:
     return {"exact": ex, "abs_sum": ab}
 
 
+def segmented_scan(spec: dict, x: torch.Tensor, offsets: torch.Tensor, exclusive: bool = False) -> dict:
+    """Prefix sums restarting at every segment start: the scan definition applied to each segment
+    [offsets[j], offsets[j+1]) on its own.  Arrays over all n positions; positions outside every
+    segment hold NaN (floats) or 0 (int32) and are not part of the result."""
+    x = _host(x)
+    off = _host(offsets).to(torch.int64)
+    n = x.numel()
+    f = make_fn(spec)
+    es = x.element_size()
+    is_int = x.dtype == torch.int32
+    if is_int:
+        out = np.zeros(n, dtype=np.int64)
+    else:
+        ex = np.full(n, np.nan)
+        ab = np.full(n, np.nan)
+    for j in range(off.numel() - 1):
+        lo, hi = int(off[j]), int(off[j + 1])
+        if hi <= lo:
+            continue
+        xp = x.data_ptr() + lo * es
+        if is_int:
+            rc = lib().or_scan(ctypes.byref(f), DTYPES[x.dtype], xp, hi - lo, int(exclusive), None, None,
+                               out.ctypes.data + lo * 8)
+        else:
+            rc = lib().or_scan(ctypes.byref(f), DTYPES[x.dtype], xp, hi - lo, int(exclusive),
+                               ex.ctypes.data + lo * 8, ab.ctypes.data + lo * 8, None)
+        if rc != 0:
+            raise ValueError("oracle: unsupported segmented scan")
+    return {"isum": out} if is_int else {"exact": ex, "abs_sum": ab}
+
+
 def exact_sum(v) -> float:
     """Exact sum of float64 values, rounded once to float64."""
     a = np.ascontiguousarray(np.asarray(v, dtype=np.float64))

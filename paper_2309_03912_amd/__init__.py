@@ -41,7 +41,7 @@ FN = {"identity": FN_IDENTITY, "affine": FN_AFFINE, "horner": FN_HORNER, "produc
 # Every symbol include/hdc.h declares.
 EXPORTS = [
     "hdc_map", "hdc_transform_reduce", "hdc_segmented_reduce", "hdc_map_reduce", "hdc_batch_map_reduce",
-    "hdc_host_map", "hdc_host_transform_reduce", "hdc_scan",
+    "hdc_host_map", "hdc_host_transform_reduce", "hdc_scan", "hdc_segmented_scan",
     "hdc_workspace_size", "hdc_validate_offsets", "hdc_set_tuning", "hdc_get_tuning",
     "hdc_load_tuning", "hdc_tuning_bucket", "hdc_status_string", "hdc_last_error", "hdc_version",
 ]
@@ -95,6 +95,8 @@ def lib() -> ctypes.CDLL:
         L.hdc_host_map.argtypes = [P(Functor), i32, vp, vp, i64, ctypes.c_int32]
         L.hdc_host_transform_reduce.argtypes = [P(Functor), i32, vp, vp, i64, i32, vp, ctypes.c_int32]
         L.hdc_scan.argtypes = [P(Functor), i32, vp, vp, i64, i32, ctypes.c_int32, vp, ctypes.c_size_t, vp]
+        L.hdc_segmented_scan.argtypes = [P(Functor), i32, vp, vp, i64, i64, vp, i32, ctypes.c_int32, vp,
+                                         ctypes.c_size_t, vp]
         L.hdc_workspace_size.argtypes = [i32, i32, i32, i64, i64, P(ctypes.c_size_t)]
         L.hdc_validate_offsets.argtypes = [vp, i64, i64, vp]
         L.hdc_set_tuning.argtypes = [i32, i32, i32, i32, P(Tuning)]
@@ -103,7 +105,7 @@ def lib() -> ctypes.CDLL:
         L.hdc_load_tuning.argtypes = [ctypes.c_char_p]
         for name in ["hdc_map", "hdc_transform_reduce", "hdc_segmented_reduce", "hdc_map_reduce",
                      "hdc_batch_map_reduce", "hdc_host_map", "hdc_host_transform_reduce", "hdc_scan",
-                     "hdc_workspace_size", "hdc_validate_offsets", "hdc_set_tuning", "hdc_get_tuning",
+                     "hdc_segmented_scan", "hdc_workspace_size", "hdc_validate_offsets", "hdc_set_tuning", "hdc_get_tuning",
                      "hdc_load_tuning", "hdc_tuning_bucket"]:
             getattr(L, name).restype = st
         L.hdc_status_string.argtypes = [st]
@@ -330,6 +332,30 @@ def scan(x: torch.Tensor, fn, acc="plain", exclusive: bool = False, out: torch.T
     f = make_functor(fn)
     _check(lib().hdc_scan(ctypes.byref(f), dt, x.data_ptr(), y.data_ptr(), x.numel(), a, int(exclusive),
                           ws.data_ptr(), ws.numel(), _stream(x)))
+    return y
+
+
+def segmented_scan(x: torch.Tensor, offsets: torch.Tensor, fn, acc="plain", exclusive: bool = False,
+                   total: int | None = None, out: torch.Tensor | None = None,
+                   ws: torch.Tensor | None = None) -> torch.Tensor:
+    """Prefix sums of fn(x) restarting at every segment start (offsets: int64 CSR on the GPU).
+    Positions outside every segment keep the contents of `out` (zeros when it is allocated here)."""
+    x = _gpu_tensor(x, "x")
+    offsets = _gpu_tensor(offsets, "offsets")
+    if offsets.dtype != torch.int64:
+        raise ValueError("offsets must be int64")
+    a = _acc(acc)
+    dt = _dtype(x)
+    S = offsets.numel() - 1
+    if S < 0:
+        raise ValueError("offsets needs at least one entry")
+    total = x.numel() if total is None else int(total)
+    y = torch.zeros(total, dtype=OUT_DTYPE[a], device=x.device) if out is None else _gpu_tensor(out, "out")
+    if ws is None:
+        ws = workspace(x.device, OP_SCAN, dt, a, total)
+    f = make_functor(fn)
+    _check(lib().hdc_segmented_scan(ctypes.byref(f), dt, x.data_ptr(), offsets.data_ptr(), S, total,
+                                    y.data_ptr(), a, int(exclusive), ws.data_ptr(), ws.numel(), _stream(x)))
     return y
 
 

@@ -19,7 +19,8 @@ UNITS = [("hdc_api.hip", "hdc_api", []),
          ("hdc_run_segmented.hip", "hdc_run_segmented", []),
          ("hdc_run_batch.hip", "hdc_run_batch", []),
          ("hdc_run_host.hip", "hdc_run_host", []),
-         ("hdc_run_scan.hip", "hdc_run_scan", [])] + [
+         ("hdc_run_scan.hip", "hdc_run_scan", []),
+         ("hdc_run_segscan.hip", "hdc_run_segscan", [])] + [
     ("hdc_run_map_reduce.hip", f"hdc_run_map_reduce_{t.lower()}",
      [f"-DHDC_MR_STORAGE={t}", f"-DHDC_MR_NAME=run_map_reduce_{t.lower()}"]) for t in ("F32", "F16", "BF16", "I32")]
 

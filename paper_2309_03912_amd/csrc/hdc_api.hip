@@ -460,6 +460,32 @@ hdc_status hdc_scan(const hdc_functor* f, hdc_dtype dt, const void* x, void* y, 
   return run_scan(*f, dt, x, y, n, acc, exclusive, ws, t, st);
 }
 
+hdc_status hdc_segmented_scan(const hdc_functor* f, hdc_dtype dt, const void* x, const int64_t* offsets,
+                              int64_t num_segments, int64_t total, void* y, hdc_accum acc, int32_t exclusive,
+                              void* workspace, size_t ws_bytes, void* stream) {
+  HDC_TRY(check_functor(f, dt, false));
+  HDC_TRY(check_acc(dt, acc));
+  if (acc == HDC_ACC_EXACT) return fail(HDC_ERR_UNSUPPORTED, "EXACT is provided for transform_reduce and map_reduce");
+  if (num_segments < 0) return fail(HDC_ERR_INVALID_ARGUMENT, "num_segments is negative");
+  if (total < 0) return fail(HDC_ERR_INVALID_ARGUMENT, "total is negative");
+  if (exclusive != 0 && exclusive != 1) return fail(HDC_ERR_INVALID_ARGUMENT, "exclusive must be 0 or 1");
+  if (num_segments == 0 || total == 0) return HDC_OK;
+  if (!offsets) return fail(HDC_ERR_INVALID_ARGUMENT, "offsets is NULL");
+  if ((uintptr_t)offsets % 8) return fail(HDC_ERR_INVALID_ARGUMENT, "offsets is not 8-byte aligned");
+  HDC_TRY(check_ptr(x, dt, total, "x"));
+  const size_t osz = acc == HDC_ACC_PLAIN ? 4 : 8;
+  if (!y) return fail(HDC_ERR_INVALID_ARGUMENT, "y is NULL");
+  if ((uintptr_t)y % osz) return fail(HDC_ERR_INVALID_ARGUMENT, "y is not aligned to its element size");
+  const uintptr_t xb = (uintptr_t)x, yb = (uintptr_t)y;
+  if (xb < yb + (uintptr_t)total * osz && yb < xb + (uintptr_t)total * elem_size(dt))
+    return fail(HDC_ERR_INVALID_ARGUMENT, "x and y overlap");
+  hipStream_t st = (hipStream_t)stream;
+  const Tuning t = tuning_for(HDC_OP_SCAN, dt, acc, total);
+  void* ws = nullptr;
+  HDC_TRY(resolve_workspace(workspace, ws_bytes, scan_workspace_bytes(total), st, &ws));
+  return run_segmented_scan(*f, dt, x, offsets, num_segments, y, total, acc, exclusive, ws, t, st);
+}
+
 hdc_status hdc_workspace_size(int op, hdc_dtype dt, hdc_accum acc, int64_t n, int64_t num_segments,
                               size_t* bytes) {
   if (!bytes) return fail(HDC_ERR_INVALID_ARGUMENT, "bytes is NULL");

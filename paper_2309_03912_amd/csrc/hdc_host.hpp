@@ -176,12 +176,16 @@ hdc_status run_batch(const hdc_functor* fm, const hdc_functor& g, hdc_dtype dt, 
 
 hdc_status run_scan(const hdc_functor& f, hdc_dtype dt, const void* x, void* y, int64_t n, hdc_accum acc,
                     int exclusive, void* ws, const Tuning& t, hipStream_t st);
-// Workspace of a scan, for tiles of at least 64 * 16 elements: the larger of
-// the three-pass need (tile sums and offsets, 8 bytes each per tile) and the
-// single-pass need (256-byte header, then 2 + 2 words of 8 bytes per tile).
+hdc_status run_segmented_scan(const hdc_functor& f, hdc_dtype dt, const void* x, const int64_t* off,
+                              int64_t nseg, void* y, int64_t n, hdc_accum acc, int exclusive, void* ws,
+                              const Tuning& t, hipStream_t st);
+// Workspace of a scan (also segmented), for tiles of at least 64 * 16
+// elements: the larger of the three-pass need (tile sums and offsets, at most
+// 16 bytes each per tile) and the single-pass need (256-byte header, then at
+// most 3 words of 8 bytes per tile).
 inline size_t scan_workspace_bytes(int64_t n) {
   const int64_t G = n / 1024 + 1;
-  return 256 + 4 * round_up((size_t)G * 8, 256);
+  return 256 + 2 * round_up((size_t)G * 24, 256);
 }
 
 // The host side (hdc_host_map / hdc_host_transform_reduce).

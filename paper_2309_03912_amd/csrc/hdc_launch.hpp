@@ -175,13 +175,14 @@ hdc_status launch_batch(const FM& fm, const F& f, const hdc_batch_call* calls, c
 }
 
 // Scan: t.unroll == 1 selects the three-pass schedule, any other value the
-// single pass.  Workspace (scan_workspace_bytes):
+// single pass.  `seg` carries the segment offsets of a segmented scan (Acc a
+// SegAcc), else nothing.  Workspace (scan_workspace_bytes):
 //   three passes: tile sums | tile offsets, one fold state per tile each;
-//   single pass:  256-byte header (ticket, status) | 2 words per tile (the
-//                 tile's tree node).
+//   single pass:  256-byte header (ticket, status) | the tiles' tree nodes,
+//                 kWords 8-byte words each.
 template <class F, class S, class Acc>
-hdc_status launch_scan(const F& f, const void* x, void* y, int64_t n, int exclusive, void* ws, const Tuning& t,
-                       hipStream_t st) {
+hdc_status launch_scan(const F& f, const void* x, void* y, int64_t n, int exclusive, SegSpec seg, void* ws,
+                       const Tuning& t, hipStream_t st) {
   using T = typename S::T;
   using OutT = typename ScanOut<Acc>::T;
   const int64_t tile = (int64_t)t.block * kScanE;
@@ -193,38 +194,38 @@ hdc_status launch_scan(const F& f, const void* x, void* y, int64_t n, int exclus
   const dim3 grid((unsigned)G), block(t.block);
   if (t.unroll != 1) {
     uint64_t* w = static_cast<uint64_t*>(ws);
-    const int64_t nwords = 32 + 2 * G;
+    const int64_t nwords = 32 + (int64_t)ScanCarry<Acc>::kWords * G;
     const ScanLB lb{static_cast<uint32_t*>(ws), static_cast<uint32_t*>(ws) + 1, w + 32};
     const int64_t cb = (nwords + 255) / 256;
     scan_lb_clear_kernel<<<dim3((unsigned)(cb < 1024 ? cb : 1024)), dim3(256), 0, st>>>(w, nwords);
     HDC_TRY(check_launch("scan look-back clear launch"));
     if (xa && ya)
-      scan_onepass_kernel<F, S, Acc, true, true><<<grid, block, 0, st>>>(f, xp, n, lb, yp, exclusive);
+      scan_onepass_kernel<F, S, Acc, true, true><<<grid, block, 0, st>>>(f, xp, n, seg, lb, yp, exclusive);
     else if (xa)
-      scan_onepass_kernel<F, S, Acc, true, false><<<grid, block, 0, st>>>(f, xp, n, lb, yp, exclusive);
+      scan_onepass_kernel<F, S, Acc, true, false><<<grid, block, 0, st>>>(f, xp, n, seg, lb, yp, exclusive);
     else if (ya)
-      scan_onepass_kernel<F, S, Acc, false, true><<<grid, block, 0, st>>>(f, xp, n, lb, yp, exclusive);
+      scan_onepass_kernel<F, S, Acc, false, true><<<grid, block, 0, st>>>(f, xp, n, seg, lb, yp, exclusive);
     else
-      scan_onepass_kernel<F, S, Acc, false, false><<<grid, block, 0, st>>>(f, xp, n, lb, yp, exclusive);
+      scan_onepass_kernel<F, S, Acc, false, false><<<grid, block, 0, st>>>(f, xp, n, seg, lb, yp, exclusive);
     return check_launch("scan single-pass launch");
   }
   Acc* sums = static_cast<Acc*>(ws);
   Acc* offsets = reinterpret_cast<Acc*>(static_cast<char*>(ws) + round_up((size_t)G * sizeof(Acc), 256));
   if (xa)
-    scan_tile_sums_kernel<F, S, Acc, true><<<grid, block, 0, st>>>(f, xp, n, sums);
+    scan_tile_sums_kernel<F, S, Acc, true><<<grid, block, 0, st>>>(f, xp, n, seg, sums);
   else
-    scan_tile_sums_kernel<F, S, Acc, false><<<grid, block, 0, st>>>(f, xp, n, sums);
+    scan_tile_sums_kernel<F, S, Acc, false><<<grid, block, 0, st>>>(f, xp, n, seg, sums);
   HDC_TRY(check_launch("scan tile-sum launch"));
   scan_offsets_kernel<Acc><<<dim3(1), dim3(1024), 0, st>>>(sums, G, offsets);
   HDC_TRY(check_launch("scan offset launch"));
   if (xa && ya)
-    scan_tiles_kernel<F, S, Acc, true, true><<<grid, block, 0, st>>>(f, xp, n, offsets, yp, exclusive);
+    scan_tiles_kernel<F, S, Acc, true, true><<<grid, block, 0, st>>>(f, xp, n, seg, offsets, yp, exclusive);
   else if (xa)
-    scan_tiles_kernel<F, S, Acc, true, false><<<grid, block, 0, st>>>(f, xp, n, offsets, yp, exclusive);
+    scan_tiles_kernel<F, S, Acc, true, false><<<grid, block, 0, st>>>(f, xp, n, seg, offsets, yp, exclusive);
   else if (ya)
-    scan_tiles_kernel<F, S, Acc, false, true><<<grid, block, 0, st>>>(f, xp, n, offsets, yp, exclusive);
+    scan_tiles_kernel<F, S, Acc, false, true><<<grid, block, 0, st>>>(f, xp, n, seg, offsets, yp, exclusive);
   else
-    scan_tiles_kernel<F, S, Acc, false, false><<<grid, block, 0, st>>>(f, xp, n, offsets, yp, exclusive);
+    scan_tiles_kernel<F, S, Acc, false, false><<<grid, block, 0, st>>>(f, xp, n, seg, offsets, yp, exclusive);
   return check_launch("scan tile launch");
 }
 

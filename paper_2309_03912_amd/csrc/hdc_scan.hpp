@@ -94,12 +94,79 @@ struct ScanOut<IntAcc> {
   __device__ static T value(const IntAcc& a) { return (int64_t)a.s; }
 };
 
+// Fold state of a segmented scan: the state of the open segment and whether
+// a segment starts inside the span it covers.  merge(x, y) = y when y holds a
+// segment start, else x + y: associative, so every schedule above applies.
+template <class Acc>
+struct SegAcc {
+  Acc a;
+  uint32_t f;
+  __device__ static SegAcc zero() { return {Acc::zero(), 0u}; }
+  __device__ static SegAcc merge(SegAcc x, SegAcc y) { return y.f ? y : SegAcc{Acc::merge(x.a, y.a), x.f}; }
+  template <class T>
+  __device__ void add(T t) {
+    a.add(t);
+  }
+};
+template <class Acc>
+struct ScanOut<SegAcc<Acc>> {
+  using T = typename ScanOut<Acc>::T;
+  __device__ static T value(const SegAcc<Acc>& s) { return ScanOut<Acc>::value(s.a); }
+};
+
+template <class Acc>
+struct IsSeg : std::false_type {};
+template <class Acc>
+struct IsSeg<SegAcc<Acc>> : std::true_type {};
+
+// Segment boundaries of a segmented scan: the CSR offsets (m = S + 1 of them).
+struct SegSpec {
+  const int64_t* off;
+  int64_t m;
+};
+
+constexpr int64_t kNoBoundary = INT64_MAX;
+
+// First index i in [0, m) with off[i] >= p (m if none), by one wavefront:
+// every round probes 64 evenly spaced offsets, so 100,000 segments take three
+// rounds.  The result is wavefront-uniform.
+__device__ __forceinline__ int64_t wave_lower_bound(const int64_t* __restrict__ off, int64_t m, int64_t p,
+                                                    int lane) {
+  int64_t lo = 0, hi = m;  // the answer is in [lo, hi]; off[hi] >= p or hi == m
+  while (hi - lo > 64) {
+    const int64_t step = (hi - lo + 63) / 64;
+    int64_t idx = lo + (int64_t)(lane + 1) * step - 1;
+    if (idx > hi - 1) idx = hi - 1;
+    const uint64_t ge = __builtin_amdgcn_ballot_w64(off[idx] >= p);
+    if (ge == 0) return hi;
+    const int f = __builtin_ctzll(ge);
+    const int64_t nhi = lo + (int64_t)(f + 1) * step - 1;
+    lo = f == 0 ? lo : lo + (int64_t)f * step;
+    hi = nhi < hi - 1 ? nhi : hi - 1;
+  }
+  const bool in = lane < hi - lo;
+  const uint64_t ge = __builtin_amdgcn_ballot_w64(in && off[lo + (in ? lane : 0)] >= p);
+  return ge == 0 ? hi : lo + __builtin_ctzll(ge);
+}
+
+__device__ __forceinline__ int64_t read_lane_i64(int64_t v, int lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), lane);
+  return (int64_t)((uint64_t)lo | ((uint64_t)hi << 32));
+}
+
 // One wavefront's part of a tile: loading, terms, the fold states of the
-// fixed order above, and the outputs.
+// fixed order above, and the outputs.  For a segmented scan (Acc a SegAcc)
+// the wavefront also marks the segment starts inside its part: it finds the
+// first boundary at or after its start with a 64-way search of the offsets,
+// holds the next 64 boundaries in its lanes, and sets bit e of head[q] in the
+// lane that owns each boundary position.  Outputs are written only inside
+// [off[0], off[S]).
 template <class F, class S, class Acc>
 struct ScanWave {
   static constexpr int V = S::kVec;
   static constexpr int Q = kScanE / V;
+  static constexpr bool kSeg = IsSeg<Acc>::value;
   using OutT = typename ScanOut<Acc>::T;
 
   int64_t wbase;  // first element of this wavefront's part
@@ -110,11 +177,13 @@ struct ScanWave {
   Acc ex[Q];                       // exclusive prefix of this lane within chunk q
   Acc wc[Q];                       // fold of chunks 0..q-1 of this wavefront
   Acc wave_total;
+  uint32_t head[Q];                // segmented: bit e set if element (q, e) starts a segment
+  int64_t out_lo, out_hi;          // segmented: outputs are written in [out_lo, out_hi)
 
   __device__ int64_t index(int q, int e) const { return wbase + (int64_t)q * 64 * V + (int64_t)lane * V + e; }
 
   template <bool kAligned>
-  __device__ void load(const elem_t<S>* x) {
+  __device__ void load(const elem_t<S>* x, const SegSpec& seg) {
     if (kAligned && wbase + 64 * kScanE <= n) {
       Vec<S> a[Q];
 #pragma unroll
@@ -132,6 +201,57 @@ struct ScanWave {
           v[q * V + e] = i < n ? x[i] : elem_t<S>{};
         }
     }
+    if constexpr (kSeg) mark_heads(seg);  // overlaps the loads in flight
+  }
+
+  __device__ void mark_heads(const SegSpec& seg) {
+    out_lo = seg.off[0];
+    out_hi = seg.off[seg.m - 1];
+    int64_t base = wave_lower_bound(seg.off, seg.m, wbase, lane);
+    int at = 0;
+    int64_t mine = base + lane < seg.m ? seg.off[base + lane] : kNoBoundary;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      head[q] = 0;
+      const int64_t c0 = wbase + (int64_t)q * 64 * V, c1 = c0 + 64 * V;
+      for (;;) {  // wavefront-uniform: the boundaries in [c0, c1), in order
+        const int64_t b = read_lane_i64(mine, at);
+        if (b >= c1) break;
+        const int64_t d = b - c0;  // >= 0: earlier boundaries were consumed before
+        if (lane == (int)(d / V)) head[q] |= 1u << (int)(d % V);
+        if (++at == 64) {
+          base += 64;
+          at = 0;
+          mine = base + lane < seg.m ? seg.off[base + lane] : kNoBoundary;
+        }
+      }
+    }
+  }
+
+  __device__ bool is_head(int q, int e) const {
+    if constexpr (kSeg)
+      return (head[q] >> e) & 1u;
+    else
+      return false;
+  }
+
+  // Fold element (q, e) into a; a segment start first resets it.
+  __device__ void accum(Acc& a, const F& f, int q, int e) const {
+    if constexpr (kSeg) {
+      if (is_head(q, e)) {
+        a = Acc::zero();
+        a.f = 1u;
+      }
+      if constexpr (!std::is_same_v<S, I32>)
+        a.add(t[q * V + e]);
+      else
+        fold_elem<F, S>(a.a, f, v[q * V + e], v[q * V + e]);
+    } else {
+      if constexpr (!std::is_same_v<S, I32>)
+        a.add(t[q * V + e]);
+      else
+        fold_elem<F, S>(a, f, v[q * V + e], v[q * V + e]);
+    }
   }
 
   // Terms, lane totals per chunk, the wavefront scans and the chunk chain.
@@ -141,21 +261,13 @@ struct ScanWave {
 #pragma unroll
       for (int k = 0; k < kScanE; ++k) t[k] = S::widen(v[k]);
       eval_batch(f, t);  // once: the terms serve the totals and the outputs
+    }
 #pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        tot[q] = Acc::zero();
+    for (int q = 0; q < Q; ++q) {
+      tot[q] = Acc::zero();
 #pragma unroll
-        for (int e = 0; e < V; ++e)
-          if (index(q, e) < n) tot[q].add(t[q * V + e]);
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        tot[q] = Acc::zero();
-#pragma unroll
-        for (int e = 0; e < V; ++e)
-          if (index(q, e) < n) fold_elem<F, S>(tot[q], f, v[q * V + e], v[q * V + e]);
-      }
+      for (int e = 0; e < V; ++e)
+        if (index(q, e) < n) accum(tot[q], f, q, e);
     }
     Acc run = Acc::zero();
 #pragma unroll
@@ -184,20 +296,16 @@ struct ScanWave {
   template <bool kOutAligned>
   __device__ void emit(const F& f, const Acc& before, int exclusive, OutT* y) const {
     constexpr int PER = 16 / sizeof(OutT);
-    const bool full = kOutAligned && wbase + 64 * kScanE <= n;
+    bool full = kOutAligned && wbase + 64 * kScanE <= n;
+    if constexpr (kSeg) full = full && wbase >= out_lo && wbase + 64 * kScanE <= out_hi;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       Acc a = Acc::merge(Acc::merge(before, wc[q]), ex[q]);
       OutT o[V];
 #pragma unroll
       for (int e = 0; e < V; ++e) {
-        const OutT prev = ScanOut<Acc>::value(a);
-        if (index(q, e) < n) {
-          if constexpr (!std::is_same_v<S, I32>)
-            a.add(t[q * V + e]);
-          else
-            fold_elem<F, S>(a, f, v[q * V + e], v[q * V + e]);
-        }
+        const OutT prev = is_head(q, e) ? OutT{} : ScanOut<Acc>::value(a);
+        if (index(q, e) < n) accum(a, f, q, e);
         o[e] = exclusive ? prev : ScanOut<Acc>::value(a);
       }
       if (full) {
@@ -213,8 +321,12 @@ struct ScanWave {
         }
       } else {
 #pragma unroll
-        for (int e = 0; e < V; ++e)
-          if (index(q, e) < n) y[index(q, e)] = o[e];
+        for (int e = 0; e < V; ++e) {
+          const int64_t i = index(q, e);
+          bool keep = i < n;
+          if constexpr (kSeg) keep = keep && i >= out_lo && i < out_hi;
+          if (keep) y[i] = o[e];
+        }
       }
     }
   }
@@ -250,10 +362,11 @@ __device__ __forceinline__ ScanWave<F, S, Acc> scan_wave_at(int64_t tile, int64_
 // Pass A: the sum of every tile.
 template <class F, class S, class Acc, bool kAligned>
   requires device_callable<F>
-__global__ __launch_bounds__(1024) void scan_tile_sums_kernel(F f, const elem_t<S>* x, int64_t n, Acc* sums) {
+__global__ __launch_bounds__(1024) void scan_tile_sums_kernel(F f, const elem_t<S>* x, int64_t n, SegSpec seg,
+                                                              Acc* sums) {
   __shared__ Acc lds[kMaxWaves];
   auto w = scan_wave_at<F, S, Acc>(blockIdx.x, n);
-  w.template load<kAligned>(x);
+  w.template load<kAligned>(x, seg);
   w.fold(f);
   Acc total;
   (void)block_wave_prefix(w.wave_total, lds, &total);
@@ -302,11 +415,12 @@ __global__ __launch_bounds__(1024) void scan_offsets_kernel(const Acc* sums, int
 // Pass C: scan every tile again and add its offset.
 template <class F, class S, class Acc, bool kAligned, bool kOutAligned>
   requires device_callable<F>
-__global__ __launch_bounds__(1024) void scan_tiles_kernel(F f, const elem_t<S>* x, int64_t n, const Acc* offsets,
-                                                          typename ScanOut<Acc>::T* y, int exclusive) {
+__global__ __launch_bounds__(1024) void scan_tiles_kernel(F f, const elem_t<S>* x, int64_t n, SegSpec seg,
+                                                          const Acc* offsets, typename ScanOut<Acc>::T* y,
+                                                          int exclusive) {
   __shared__ Acc lds[kMaxWaves];
   auto w = scan_wave_at<F, S, Acc>(blockIdx.x, n);
-  w.template load<kAligned>(x);
+  w.template load<kAligned>(x, seg);
   w.fold(f);
   Acc total;
   const Acc before = block_wave_prefix(w.wave_total, lds, &total);
@@ -319,22 +433,37 @@ __global__ __launch_bounds__(1024) void scan_tiles_kernel(F f, const elem_t<S>* 
 
 // The carry between tiles: fp64 for the float folds (so a chain of up to
 // 2^31 tile sums adds no error that matters at fp32), the exact int64 for
-// integers.  `of` turns a tile total into a carry, `to` a carry into the
-// fold state a tile continues from.
+// integers; a segmented scan's carry adds the segment-start flag.  `of`
+// turns a tile total into a carry, `to` a carry into the fold state a tile
+// continues from; `pack` / `unpack` give its kWords 32-bit words.
 template <class Acc>
 struct ScanCarry;
+
+template <class T>
+struct Carry64 {  // a 64-bit carry as two words
+  static constexpr int kWords = 2;
+  __device__ static void pack(T c, uint32_t (&w)[2]) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, c);
+    w[0] = (uint32_t)b;
+    w[1] = (uint32_t)(b >> 32);
+  }
+  __device__ static T unpack(const uint32_t* w) {
+    return __builtin_bit_cast(T, (uint64_t)w[0] | ((uint64_t)w[1] << 32));
+  }
+};
+
 template <>
-struct ScanCarry<PlainAcc> {
+struct ScanCarry<PlainAcc> : Carry64<double> {
   using T = double;
+  __device__ static T zero() { return 0.0; }
   __device__ static T of(const PlainAcc& a) { return (double)a.s; }
   __device__ static PlainAcc to(T c) { return {(float)c}; }
   __device__ static T add(T a, T b) { return a + b; }
-  __device__ static uint64_t bits(T c) { return __builtin_bit_cast(uint64_t, c); }
-  __device__ static T from(uint64_t b) { return __builtin_bit_cast(double, b); }
 };
 template <>
-struct ScanCarry<CompAcc> {
+struct ScanCarry<CompAcc> : Carry64<double> {
   using T = double;
+  __device__ static T zero() { return 0.0; }
   __device__ static T of(const CompAcc& a) {
     return __builtin_isfinite(a.s) ? (double)a.s + (double)a.c : (double)a.s;
   }
@@ -343,29 +472,46 @@ struct ScanCarry<CompAcc> {
     return {s, __builtin_isfinite(s) ? (float)(c - (double)s) : 0.0f};
   }
   __device__ static T add(T a, T b) { return a + b; }
-  __device__ static uint64_t bits(T c) { return __builtin_bit_cast(uint64_t, c); }
-  __device__ static T from(uint64_t b) { return __builtin_bit_cast(double, b); }
 };
 template <>
-struct ScanCarry<IntAcc> {
+struct ScanCarry<IntAcc> : Carry64<uint64_t> {
   using T = uint64_t;
+  __device__ static T zero() { return 0; }
   __device__ static T of(const IntAcc& a) { return a.s; }
   __device__ static IntAcc to(T c) { return {c}; }
   __device__ static T add(T a, T b) { return a + b; }
-  __device__ static uint64_t bits(T c) { return c; }
-  __device__ static T from(uint64_t b) { return b; }
+};
+template <class Acc>
+struct ScanCarry<SegAcc<Acc>> {
+  using B = ScanCarry<Acc>;
+  struct T {
+    typename B::T v;
+    uint32_t f;
+  };
+  static constexpr int kWords = 3;
+  __device__ static T zero() { return {B::zero(), 0u}; }
+  __device__ static T of(const SegAcc<Acc>& s) { return {B::of(s.a), s.f}; }
+  __device__ static SegAcc<Acc> to(T c) { return {B::to(c.v), c.f}; }
+  __device__ static T add(T x, T y) { return y.f ? y : T{B::add(x.v, y.v), x.f}; }
+  __device__ static void pack(T c, uint32_t (&w)[3]) {
+    uint32_t h[2];
+    B::pack(c.v, h);
+    w[0] = h[0];
+    w[1] = h[1];
+    w[2] = c.f;
+  }
+  __device__ static T unpack(const uint32_t* w) { return {B::unpack(w), w[2]}; }
 };
 
-// Look-back state in the workspace: one tree node per tile.  Every 64-bit
-// value is published as two 64-bit words, each holding one 32-bit half below
-// a ready flag (bit 32), so each word is written and read by one
-// single-copy-atomic access and no fence orders a value against a separate
-// flag.  All words start at zero (scan_lb_clear_kernel runs first on the
-// same stream).
+// Look-back state in the workspace: one tree node per tile, as kWords 64-bit
+// words per tile.  Every word holds one 32-bit part of the value below a
+// ready flag (bit 32), so it is written and read by one single-copy-atomic
+// access and no fence orders a value against a separate flag.  All words
+// start at zero (scan_lb_clear_kernel runs first on the same stream).
 struct ScanLB {
   uint32_t* ticket;  // next tile to hand out
   uint32_t* status;  // nonzero: a wait gave up (the result is invalid)
-  uint64_t* node;    // 2 words per tile
+  uint64_t* node;    // kWords words per tile
 };
 
 constexpr uint32_t kLookbackSpinLimit = 1u << 16;  // polls before giving up
@@ -375,22 +521,23 @@ static __global__ __launch_bounds__(256) void scan_lb_clear_kernel(uint64_t* w, 
     w[i] = 0;
 }
 
-__device__ __forceinline__ void lb_publish(uint64_t* w, uint64_t v) {
-  __hip_atomic_store(w, (uint64_t(1) << 32) | (v & 0xffffffffu), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(w + 1, (uint64_t(1) << 32) | (v >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+template <int W>
+__device__ __forceinline__ void lb_publish(uint64_t* node, const uint32_t (&v)[W]) {
+#pragma unroll
+  for (int k = 0; k < W; ++k)
+    __hip_atomic_store(node + k, (uint64_t(1) << 32) | v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ bool lb_read(const uint64_t* w, uint64_t* v) {
-  const uint64_t lo = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const uint64_t hi = __hip_atomic_load(w + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  *v = (lo & 0xffffffffu) | (hi << 32);
-  return (lo >> 32) != 0 && (hi >> 32) != 0;
-}
-
-__device__ __forceinline__ uint64_t read_lane_u64(uint64_t v, int lane) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
-  return (uint64_t)lo | ((uint64_t)hi << 32);
+template <int W>
+__device__ __forceinline__ bool lb_read(const uint64_t* node, uint32_t (&v)[W]) {
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    const uint64_t w = __hip_atomic_load(node + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    v[k] = (uint32_t)w;
+    ok = ok && (w >> 32) != 0;
+  }
+  return ok;
 }
 
 // The carry between tiles as a binary indexed (Fenwick) tree over tile
@@ -411,6 +558,7 @@ __device__ __forceinline__ uint64_t read_lane_u64(uint64_t v, int lane) {
 // Run by one whole wavefront; lane 0 publishes node[t].
 template <class C>
 __device__ typename C::T scan_tree_carry(const ScanLB& lb, int64_t t, typename C::T own) {
+  constexpr int W = C::kWords;
   const int lane = threadIdx.x & 63;
   const uint64_t i = (uint64_t)t + 1;
   const uint64_t L = i & (~i + 1);
@@ -426,19 +574,30 @@ __device__ typename C::T scan_tree_carry(const ScanLB& lb, int64_t t, typename C
     dep = t - ((int64_t)1 << (s - 1 - (lane - r)));
   }
   bool ready = dep < 0;
-  uint64_t val = 0;
+  uint32_t val[W] = {};
+  auto entry = [&](int e) {  // the value lane e read, in every lane
+    uint32_t w[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) w[k] = (uint32_t)__builtin_amdgcn_readlane((int)val[k], e);
+    return C::unpack(w);
+  };
+  auto publish = [&](typename C::T x) {
+    uint32_t w[W];
+    C::pack(x, w);
+    lb_publish<W>(lb.node + (int64_t)W * t, w);
+  };
   bool published = false, all = false;
   const bool is_child = lane >= r && lane < r + s;
   for (uint32_t polls = 0;; ++polls) {
-    if (!ready) ready = lb_read(lb.node + 2 * dep, &val);
+    if (!ready) ready = lb_read<W>(lb.node + (int64_t)W * dep, val);
     if (!published && __builtin_amdgcn_ballot_w64(is_child && !ready) == 0) {
       typename C::T x = own;
       if (s > 0) {
-        x = C::from(read_lane_u64(val, r));
-        for (int e = r + 1; e < r + s; ++e) x = C::add(x, C::from(read_lane_u64(val, e)));
+        x = entry(r);
+        for (int e = r + 1; e < r + s; ++e) x = C::add(x, entry(e));
         x = C::add(x, own);
       }
-      if (lane == 0) lb_publish(lb.node + 2 * t, C::bits(x));
+      if (lane == 0) publish(x);
       published = true;
     }
     all = __builtin_amdgcn_ballot_w64(!ready) == 0;
@@ -447,15 +606,15 @@ __device__ typename C::T scan_tree_carry(const ScanLB& lb, int64_t t, typename C
   }
   if (!all) {  // gave up: keep the others moving, flag the result
     if (lane == 0) {
-      if (!published) lb_publish(lb.node + 2 * t, C::bits(own));
+      if (!published) publish(own);
       __hip_atomic_store(lb.status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    return C::from(0);
+    return C::zero();
   }
-  typename C::T carry = C::from(0);
+  typename C::T carry = C::zero();
   if (r + s > 0) {
-    carry = C::from(read_lane_u64(val, 0));
-    for (int e = 1; e < r + s; ++e) carry = C::add(carry, C::from(read_lane_u64(val, e)));
+    carry = entry(0);
+    for (int e = 1; e < r + s; ++e) carry = C::add(carry, entry(e));
   }
   return carry;
 }
@@ -463,8 +622,8 @@ __device__ typename C::T scan_tree_carry(const ScanLB& lb, int64_t t, typename C
 // One tile per block; the tile index comes from the ticket, not blockIdx.
 template <class F, class S, class Acc, bool kAligned, bool kOutAligned>
   requires device_callable<F>
-__global__ __launch_bounds__(1024) void scan_onepass_kernel(F f, const elem_t<S>* x, int64_t n, ScanLB lb,
-                                                            typename ScanOut<Acc>::T* y, int exclusive) {
+__global__ __launch_bounds__(1024) void scan_onepass_kernel(F f, const elem_t<S>* x, int64_t n, SegSpec seg,
+                                                            ScanLB lb, typename ScanOut<Acc>::T* y, int exclusive) {
   using C = ScanCarry<Acc>;
   __shared__ Acc lds[kMaxWaves];
   __shared__ int64_t tile_sh;
@@ -473,7 +632,7 @@ __global__ __launch_bounds__(1024) void scan_onepass_kernel(F f, const elem_t<S>
   __syncthreads();
   const int64_t tile = tile_sh;
   auto w = scan_wave_at<F, S, Acc>(tile, n);
-  w.template load<kAligned>(x);
+  w.template load<kAligned>(x, seg);
   w.fold(f);
   Acc total;
   const Acc before = block_wave_prefix(w.wave_total, lds, &total);

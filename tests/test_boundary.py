@@ -179,6 +179,29 @@ def test_host_only_callable_cannot_instantiate_a_kernel():
     assert good.returncode == 0, good.stderr
 
 
+def test_segmented_scan_rejects_bad_arguments():
+    L = hdc.lib()
+    ident = fn({"fn": "identity"})
+    need = hdc.workspace_size(hdc.OP_SCAN, hdc.F32, hdc.ACC_PLAIN, 1000)
+    args = lambda **k: (k.get("f", ident), k.get("dt", hdc.F32), k.get("x", FAKE), k.get("off", FAKE + 65536),
+                        k.get("S", 10), k.get("total", 1000), k.get("y", FAKE + 131072),
+                        k.get("acc", hdc.ACC_PLAIN), k.get("ex", 0), k.get("ws", FAKE + 262144),
+                        k.get("wsb", need), None)
+    assert L.hdc_segmented_scan(*args(S=-1)) == hdc.ERR_INVALID_ARGUMENT
+    assert L.hdc_segmented_scan(*args(total=-1)) == hdc.ERR_INVALID_ARGUMENT
+    assert L.hdc_segmented_scan(*args(ex=2)) == hdc.ERR_INVALID_ARGUMENT
+    assert L.hdc_segmented_scan(*args(off=None)) == hdc.ERR_INVALID_ARGUMENT
+    assert L.hdc_segmented_scan(*args(off=FAKE + 4)) == hdc.ERR_INVALID_ARGUMENT    # not 8-byte aligned
+    assert L.hdc_segmented_scan(*args(y=None)) == hdc.ERR_INVALID_ARGUMENT
+    assert L.hdc_segmented_scan(*args(y=FAKE)) == hdc.ERR_INVALID_ARGUMENT          # overlaps x
+    assert L.hdc_segmented_scan(*args(acc=hdc.ACC_EXACT_INT)) == hdc.ERR_UNSUPPORTED
+    assert L.hdc_segmented_scan(*args(acc=hdc.ACC_EXACT)) == hdc.ERR_UNSUPPORTED
+    assert L.hdc_segmented_scan(*args(f=fn({"fn": "product"}))) == hdc.ERR_UNSUPPORTED
+    assert L.hdc_segmented_scan(*args(wsb=need - 1)) == hdc.ERR_WORKSPACE
+    assert L.hdc_segmented_scan(*args(S=0)) == hdc.OK                 # nothing to do, nothing enqueued
+    assert L.hdc_segmented_scan(*args(total=0)) == hdc.OK
+
+
 def test_scan_rejects_bad_arguments():
     L = hdc.lib()
     ident = fn({"fn": "identity"})

@@ -1,0 +1,143 @@
+"""GPU parity of hdc_segmented_scan (prefix sums restarting at every segment start)
+against the oracle, through the C ABI, under both scan schedules.
+
+Per position inside a segment: integers bit-exact; floating point within 1e-6
+of the running sum of magnitudes of that segment's exact prefix; positions
+outside every segment are left untouched."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2309_03912_amd as hdc
+import synth
+
+pytestmark = pytest.mark.gpu
+
+HOR = {"fn": "horner", "coef": synth.horner_coefficients(8)}
+AFF = {"fn": "affine", "a": 2.5, "b": 0.5}
+IAFF = {"fn": "affine", "a": 3, "b": -7}
+CLASSES = [(hdc.F32, hdc.ACC_PLAIN), (hdc.F32, hdc.ACC_COMPENSATED), (hdc.F16, hdc.ACC_PLAIN),
+           (hdc.F16, hdc.ACC_COMPENSATED), (hdc.BF16, hdc.ACC_PLAIN), (hdc.BF16, hdc.ACC_COMPENSATED),
+           (hdc.I32, hdc.ACC_EXACT_INT)]
+
+
+def gpu():
+    return torch.device("cuda", 0)
+
+
+@pytest.fixture(params=["single_pass", "three_pass"], autouse=True)
+def schedule(request):
+    saved = {(dt, acc, b): hdc.get_tuning(hdc.OP_SCAN, dt, acc, b) for dt, acc in CLASSES for b in range(4)}
+    for dt, acc in CLASSES:
+        hdc.set_tuning(hdc.OP_SCAN, dt, acc, -1, unroll=4 if request.param == "single_pass" else 1)
+    yield request.param
+    for (dt, acc, b), t in saved.items():
+        hdc.set_tuning(hdc.OP_SCAN, dt, acc, b, **t)
+
+
+def edge_lengths(seed, count):
+    """Empty, one-element and tile-straddling segments among random lengths."""
+    rng = np.random.default_rng(seed)
+    special = [0, 0, 1, 1, 2, 3, 4, 5, 63, 64, 65, 255, 256, 257, 1023, 1024, 1025, 4096, 16383, 16384, 16385,
+               40000, 0, 1]
+    L = special + rng.integers(0, 2000, count - len(special)).tolist()
+    rng.shuffle(L)
+    return torch.tensor(L, dtype=torch.int64)
+
+
+def inside(off, n):
+    m = np.zeros(n, dtype=bool)
+    for j in range(off.numel() - 1):
+        m[int(off[j]):int(off[j + 1])] = True
+    return m
+
+
+def check_float(got, ref, mask, what):
+    got = got.cpu().double().numpy()
+    err = np.abs(got - ref["exact"])
+    bad = np.where(mask & ~(err <= 1e-6 * ref["abs_sum"]))[0]
+    assert bad.size == 0, f"{what}: {bad.size} positions off, first {bad[:5]}"
+
+
+@pytest.mark.parametrize("acc", ["plain", "compensated"])
+@pytest.mark.parametrize("dt", [torch.float32, torch.float16, torch.bfloat16])
+def test_segscan_float(dt, acc):
+    L = edge_lengths(1, 300)
+    off = synth.offsets_from_lengths(L)
+    n = int(off[-1])
+    x = synth.to_storage(synth.uniform_pm1_f32(11, 0, n).double(), dt)
+    mask = inside(off, n)
+    for fn in (HOR, AFF):
+        for ex in (False, True):
+            y = hdc.segmented_scan(x.to(gpu()), off.to(gpu()), fn, acc, exclusive=ex)
+            check_float(y, oracle.segmented_scan(fn, x, off, ex), mask, f"{fn['fn']} {dt} {acc} ex={ex}")
+
+
+def test_segscan_int_bit_exact():
+    L = edge_lengths(2, 300)
+    off = synth.offsets_from_lengths(L)
+    n = int(off[-1])
+    x = synth.uniform_int(12, 10, n)
+    for ex in (False, True):
+        y = hdc.segmented_scan(x.to(gpu()), off.to(gpu()), IAFF, "exact_int", exclusive=ex)
+        ref = oracle.segmented_scan(IAFF, x, off, ex)["isum"]
+        assert np.array_equal(y.cpu().numpy(), ref), ex
+
+
+def test_segscan_gaps_base_and_misaligned():
+    """Offsets starting past 0 and ending before total; x an unaligned view; untouched outside."""
+    base = synth.uniform_pm1_f32(13, 0, 200011)
+    xs = base[3:]
+    n = xs.numel()
+    L = edge_lengths(3, 120)
+    off = synth.offsets_from_lengths(L) + 17
+    assert int(off[-1]) < n
+    out = torch.full((n,), 7.0, device=gpu())
+    y = hdc.segmented_scan(base.to(gpu())[3:], off.to(gpu()), AFF, "plain", out=out)
+    mask = inside(off, n)
+    check_float(y, oracle.segmented_scan(AFF, xs, off), mask, "gaps")
+    assert torch.all(y.cpu()[torch.from_numpy(~mask)] == 7.0)
+
+
+def test_segscan_single_segment_equals_scan_and_deterministic(schedule):
+    x = synth.uniform_pm1_f32(14, 0, (1 << 20) + 5).to(gpu())
+    n = x.numel()
+    off = torch.tensor([0, n], device=gpu())
+    a = hdc.segmented_scan(x, off, HOR, "compensated")
+    b = hdc.segmented_scan(x, off, HOR, "compensated")
+    assert torch.equal(a, b)
+    s = hdc.scan(x, HOR, "compensated")
+    assert torch.allclose(a, s, rtol=1e-12, atol=0)
+    ws = hdc.workspace(gpu(), hdc.OP_SCAN, hdc.F32, hdc.ACC_PLAIN, n)
+    L = edge_lengths(4, 500)
+    off2 = synth.offsets_from_lengths(L)
+    m = int(off2[-1])
+    x2 = synth.uniform_pm1_f32(15, 0, m)
+    y = hdc.segmented_scan(x2.to(gpu()), off2.to(gpu()), HOR, "plain", ws=ws)
+    if schedule == "single_pass":
+        torch.cuda.synchronize()
+        assert int(ws[4:8].cpu().view(torch.int32).item()) == 0
+    check_float(y, oracle.segmented_scan(HOR, x2, off2), inside(off2, m), "many segments")
+
+
+def test_segscan_lognormal_full_size_sampled():
+    """100,000 lognormal segments (~1.3e8 elements): sampled positions against the oracle."""
+    seed = synth.seed_of(4)
+    L = synth.segment_lengths(seed)
+    off = synth.offsets_from_lengths(L)
+    n = int(off[-1])
+    xg = synth.uniform_pm1_f32(seed, synth.STREAM["x"], n, gpu())
+    y = hdc.segmented_scan(xg, off.to(gpu()), HOR, "plain").cpu()
+    xc = xg.cpu()
+    rng = np.random.default_rng(5)
+    segs = rng.integers(0, L.numel(), 300)
+    for j in segs:
+        lo, hi = int(off[j]), int(off[j + 1])
+        if hi == lo:
+            continue
+        for i in {lo, hi - 1, int(rng.integers(lo, hi))}:
+            r = oracle.reduce(HOR, xc[lo:i + 1])
+            assert abs(float(y[i]) - r["exact"]) <= 1e-6 * r["abs_sum"], (j, i)
+    del xg
+    torch.cuda.empty_cache()

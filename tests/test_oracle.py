@@ -414,3 +414,40 @@ def test_scan_matches_fsum_prefixes_and_reduce():
     rex = oracle.scan(HORNER, x, exclusive=True)
     assert rex["exact"][0] == 0.0 and np.array_equal(rex["exact"][1:], r["exact"][:-1])
     assert np.all(np.diff(r["abs_sum"]) >= 0)
+
+
+def test_segmented_scan_single_segment_equals_scan():
+    x = synth.uniform_pm1_f32(6, 0, 2000)
+    whole = torch.tensor([0, 2000])
+    for ex in (False, True):
+        a = oracle.segmented_scan(HORNER, x, whole, ex)
+        b = oracle.scan(HORNER, x, ex)
+        assert np.array_equal(a["exact"], b["exact"]) and np.array_equal(a["abs_sum"], b["abs_sum"])
+
+
+def test_segmented_scan_brute_force():
+    """Tiny segments (empty ones included, and a gap before the first): every prefix is the fsum of the
+    terms from its segment's start; the last prefix of a segment equals the segmented reduce."""
+    x = synth.uniform_pm1_f32(7, 0, 400)
+    terms = oracle.map(HORNER, x).double().tolist()
+    off = torch.tensor([5, 5, 9, 40, 41, 41, 200, 399])
+    r = oracle.segmented_scan(HORNER, x, off)
+    rex = oracle.segmented_scan(HORNER, x, off, exclusive=True)
+    red = oracle.segmented(HORNER, x, off)
+    for j in range(off.numel() - 1):
+        lo, hi = int(off[j]), int(off[j + 1])
+        for i in range(lo, hi):
+            assert r["exact"][i] == math.fsum(terms[lo:i + 1])
+            assert rex["exact"][i] == math.fsum(terms[lo:i])
+        if hi > lo:
+            assert r["exact"][hi - 1] == red["exact"][j]
+    outside = np.r_[0:5, 399:400]
+    assert np.all(np.isnan(r["exact"][outside]))
+    xi = synth.uniform_int(8, 0, 400)
+    ri = oracle.segmented_scan({"fn": "affine", "a": 3, "b": -7}, xi, off)["isum"]
+    for j in range(off.numel() - 1):
+        lo, hi = int(off[j]), int(off[j + 1])
+        acc = 0
+        for i in range(lo, hi):
+            acc += 3 * int(xi[i]) - 7
+            assert ri[i] == acc
