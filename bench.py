@@ -253,17 +253,16 @@ def form_precision(args, torch, hdc, synth):
                 entry["comp_err"] = err_fields(rc, ref)
                 entry["plain_f32_err"] = err_fields(rp, ref)
             res[op] = entry
-        if dt == torch.float16:
-            # exact fp16 sums: the correctly rounded exact sum, independent of order and tuning
-            for op, arr in (("sum_x", x), ("sum_v_kappa", v)):
-                fe = lambda: hdc.transform_reduce(arr, ident, "exact")
-                te = ev_time(torch, fe)
-                entry = {"exact_ms": round(te, 5), "exact_GBps": round(gbps(2 * n, te), 1)}
-                if not args.no_check:
-                    import oracle
-                    exact = info["target"] if op == "sum_v_kappa" else oracle.reduce(ident, x)["exact"]
-                    entry["exact_bits_equal_oracle"] = fe().item() == exact
-                res[op].update(entry)
+        # exact 16-bit sums: the correctly rounded exact sum, independent of order and tuning
+        for op, arr in (("sum_x", x), ("sum_v_kappa", v)):
+            fe = lambda: hdc.transform_reduce(arr, ident, "exact")
+            te = ev_time(torch, fe)
+            entry = {"exact_ms": round(te, 5), "exact_GBps": round(gbps(2 * n, te), 1)}
+            if not args.no_check:
+                import oracle
+                exact = info["target"] if op == "sum_v_kappa" else oracle.reduce(ident, x)["exact"]
+                entry["exact_bits_equal_oracle"] = fe().item() == exact
+            res[op].update(entry)
         out[name] = res
         del x, z, v, xf, zf, vf
         torch.cuda.empty_cache()

@@ -79,11 +79,12 @@ typedef enum hdc_accum {
                               final cross-block combine; `out` is one double */
   HDC_ACC_EXACT_INT = 2,   /* int32: int64 sums wrapping mod 2^64; `out` is
                               one int64 */
-  HDC_ACC_EXACT = 3        /* fp16 storage, IDENTITY fold: the exact real sum
-                              rounded once to fp64 (nearest-even); `out` is
-                              one double.  Independent of order and tuning:
-                              bit-reproducible.  transform_reduce and
-                              map_reduce only. */
+  HDC_ACC_EXACT = 3        /* fp16 or bf16 storage, IDENTITY fold: the
+                              exact real sum rounded once to fp64
+                              (nearest-even); `out` is one double.
+                              Independent of order and tuning:
+                              bit-reproducible.  transform_reduce (fp16 and
+                              bf16) and map_reduce (fp16) only. */
 } hdc_accum;
 
 typedef enum hdc_op {

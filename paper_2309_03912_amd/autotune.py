@@ -75,7 +75,8 @@ class Case:
         self.aff = {"fn": "affine", "a": 3, "b": -7} if dt == I32 else {"fn": "affine", "a": 2.5, "b": 0.5}
         self.ident = {"fn": "identity"}
         self.y = torch.empty_like(self.x)
-        accname = {ACC_PLAIN: "plain", ACC_COMPENSATED: "compensated", ACC_EXACT_INT: "exact_int"}[acc]
+        accname = {ACC_PLAIN: "plain", ACC_COMPENSATED: "compensated", ACC_EXACT_INT: "exact_int",
+                   ACC_EXACT: "exact"}[acc]
         self.accname = accname
         if op == OP_BATCH:
             # `segments` holds the call sizes of the batch
@@ -98,7 +99,8 @@ class Case:
         elif op != OP_MAP:
             self.ws = workspace(dev, op, dt, acc, n)
             self.out = torch.empty((), dtype={ACC_PLAIN: torch.float32, ACC_COMPENSATED: torch.float64,
-                                              ACC_EXACT_INT: torch.int64}[acc], device=dev)
+                                              ACC_EXACT_INT: torch.int64, ACC_EXACT: torch.float64}[acc],
+                                   device=dev)
         if op == OP_DOT:
             self.z = _inputs(dt, n, dev, seed=2)
 
@@ -114,7 +116,7 @@ class Case:
         if self.op == OP_MAP:
             hdc_map(self.x, self.aff, out=self.y)
         elif self.op == OP_TRANSFORM_REDUCE:
-            fn = self.ident if self.dt == I32 else self.horner
+            fn = self.ident if self.dt == I32 or self.acc == ACC_EXACT else self.horner
             transform_reduce(self.x, fn, self.accname, out=self.out, ws=self.ws)
         elif self.op == OP_DOT:
             transform_reduce(self.x, {"fn": "product"}, self.accname, z=self.z, out=self.out, ws=self.ws)
@@ -154,7 +156,7 @@ class Case:
                            b.view(torch.int16) if b.element_size() == 2 else b.view(torch.int32))
 
     def agrees_sum(self, a, b):
-        if self.acc == ACC_EXACT_INT:
+        if self.acc in (ACC_EXACT_INT, ACC_EXACT):
             return torch.equal(a, b)
         a, b = a.double(), b.double()
         return bool(((a - b).abs() <= 2e-6 * torch.maximum(a.abs(), b.abs()) + 1e-30).all())
@@ -230,6 +232,8 @@ def default_cases(dev, quick=False, log2n=28):
         Case(OP_TRANSFORM_REDUCE, BF16, ACC_COMPENSATED, n, dev),
         Case(OP_TRANSFORM_REDUCE, F16, ACC_COMPENSATED, n, dev),
         Case(OP_TRANSFORM_REDUCE, F32, ACC_COMPENSATED, n, dev),
+        Case(OP_TRANSFORM_REDUCE, BF16, ACC_EXACT, n, dev),
+        Case(OP_TRANSFORM_REDUCE, F16, ACC_EXACT, n, dev),
         Case(OP_DOT, F32, ACC_PLAIN, n, dev),
         Case(OP_DOT, BF16, ACC_COMPENSATED, n, dev),
         Case(OP_DOT, F16, ACC_COMPENSATED, n, dev),

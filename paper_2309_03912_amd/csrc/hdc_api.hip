@@ -237,7 +237,8 @@ hdc_status check_functor(const hdc_functor* f, hdc_dtype dt, bool allow_product)
 hdc_status check_acc(hdc_dtype dt, hdc_accum acc) {
   if (acc != HDC_ACC_PLAIN && acc != HDC_ACC_COMPENSATED && acc != HDC_ACC_EXACT_INT && acc != HDC_ACC_EXACT)
     return fail(HDC_ERR_INVALID_ARGUMENT, "unknown accumulation %d", (int)acc);
-  if (acc == HDC_ACC_EXACT && dt != HDC_F16) return fail(HDC_ERR_UNSUPPORTED, "EXACT needs fp16 storage");
+  if (acc == HDC_ACC_EXACT && dt != HDC_F16 && dt != HDC_BF16)
+    return fail(HDC_ERR_UNSUPPORTED, "EXACT needs fp16 or bf16 storage");
   if (is_float(dt) && acc == HDC_ACC_EXACT_INT)
     return fail(HDC_ERR_UNSUPPORTED, "EXACT_INT needs int32 storage");
   if (dt == HDC_I32 && acc != HDC_ACC_EXACT_INT)
@@ -283,6 +284,8 @@ static hdc_status reduce_common(const hdc_functor* f, const hdc_functor* fm, hdc
   HDC_TRY(check_acc(dt, acc));
   if (acc == HDC_ACC_EXACT && f->id != HDC_FN_IDENTITY)
     return fail(HDC_ERR_UNSUPPORTED, "EXACT folds the IDENTITY callable only");
+  if (acc == HDC_ACC_EXACT && fused && dt != HDC_F16)
+    return fail(HDC_ERR_UNSUPPORTED, "EXACT map_reduce is provided for fp16 storage");
   if (n < 0) return fail(HDC_ERR_INVALID_ARGUMENT, "n = %lld is negative", (long long)n);
   HDC_TRY(check_ptr(x, dt, n, "x"));
   if (f->id == HDC_FN_PRODUCT) {

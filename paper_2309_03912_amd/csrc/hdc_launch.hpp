@@ -5,6 +5,7 @@
 #include <type_traits>
 
 #include "hdc_batch.hpp"
+#include "hdc_exact.hpp"
 #include "hdc_host.hpp"
 #include "hdc_scan.hpp"
 
@@ -73,6 +74,31 @@ hdc_status launch_reduce(const F& f, const void* x, const void* z, int64_t n, vo
   return launch_final<Acc>(partials, g, out, st);
 }
 
+
+// Exact bf16 sum: pass 1 over t.block threads x t.unroll vectors per step
+// (1, 2 or 4), at most 4096 blocks (their 88-byte partials fit the reduce
+// workspace), then the one-block final combine and rounding.
+inline hdc_status launch_exact_bf16(const void* x, int64_t n, void* out, void* ws, const Tuning& t,
+                                    hipStream_t st) {
+  int cus = 0;
+  HDC_TRY(compute_units(&cus));
+  const Range r = make_range<BF16>(x, n, true);
+  const int u = t.unroll >= 4 ? 4 : t.unroll;
+  int64_t g = grid_for(r.nvec, (int64_t)t.block * u, cus, t);
+  if (g > 4096) g = 4096;
+  Bf16Exact* partials = static_cast<Bf16Exact*>(ws);
+  const uint16_t* xp = static_cast<const uint16_t*>(x);
+  const dim3 grid((unsigned)g), block(t.block);
+  if (u == 1)
+    exact_bf16_kernel<1><<<grid, block, 0, st>>>(xp, r, partials);
+  else if (u == 2)
+    exact_bf16_kernel<2><<<grid, block, 0, st>>>(xp, r, partials);
+  else
+    exact_bf16_kernel<4><<<grid, block, 0, st>>>(xp, r, partials);
+  HDC_TRY(check_launch("exact bf16 launch"));
+  exact_bf16_final_kernel<<<dim3(1), dim3(256), 0, st>>>(partials, (int)g, static_cast<double*>(out));
+  return check_launch("exact bf16 final launch");
+}
 
 template <class F, class S, class Acc>
 hdc_status launch_segmented(const F& f, const void* x, const int64_t* off, int64_t nseg, int64_t total, void* out,

@@ -88,7 +88,7 @@ def test_transform_reduce_rejects_bad_arguments():
     assert L.hdc_transform_reduce(*args(f=fn({"fn": "product"}), z=FAKE + 1)) == hdc.ERR_INVALID_ARGUMENT
     assert L.hdc_transform_reduce(*args(dt=hdc.I32, acc=hdc.ACC_EXACT_INT,
                                         f=fn({"fn": "horner", "coef": [1.0]}))) == hdc.ERR_UNSUPPORTED
-    assert L.hdc_transform_reduce(*args(acc=hdc.ACC_EXACT)) == hdc.ERR_UNSUPPORTED            # exact: fp16 only
+    assert L.hdc_transform_reduce(*args(acc=hdc.ACC_EXACT)) == hdc.ERR_UNSUPPORTED            # exact: 16-bit only
     assert L.hdc_transform_reduce(*args(acc=hdc.ACC_EXACT, dt=hdc.F16,
                                         f=fn({"fn": "horner", "coef": [1.0]}))) == hdc.ERR_UNSUPPORTED
     assert L.hdc_transform_reduce(*args(wsb=need - 1)) == hdc.ERR_WORKSPACE

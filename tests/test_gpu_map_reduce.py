@@ -326,6 +326,64 @@ def test_exact_fp16_nonfinite_and_fused():
     assert r.item() == oracle.reduce({"fn": "identity"}, x)["exact"]
 
 
+# --------------------------------------------------------------------------
+# exact bf16 sums: the full bf16 range (2^-133 .. 2^128) in 32-bit digits
+# --------------------------------------------------------------------------
+
+def _bf16_cases():
+    yield "normal", synth.to_storage(synth.normal_f64(61, 0, (1 << 20) + 5), torch.bfloat16)
+    yield "wide", synth.to_storage(synth.normal_f64(62, 0, 300007) * torch.exp(
+        15.0 * synth.normal_f64(62, 1, 300007)), torch.bfloat16)  # magnitudes over ~220 binary orders
+    v, _ = synth.ill_conditioned(synth.seed_of(3), 1 << 20, torch.bfloat16)
+    yield "kappa1e8", v
+    big = float(torch.finfo(torch.bfloat16).max)
+    sub = 2.0 ** -133
+    yield "extremes", torch.tensor([big, big, -big, sub, -sub, sub, 2.0 ** -126, 1.0, -0.0, big, -big, -big,
+                                    sub * 127, 3.0], dtype=torch.bfloat16)
+    yield "cancel_to_subnormal", torch.tensor([big, sub, -big], dtype=torch.bfloat16)
+    yield "all_max", torch.full((70001,), big, dtype=torch.bfloat16)  # sum far above any bf16
+    for n in (0, 1, 7, 8, 9, 4097):
+        yield f"n{n}", synth.to_storage(synth.uniform_pm1_f32(n + 70, 0, n).double() * 1e30, torch.bfloat16)
+
+
+def test_exact_bf16_sum_is_bit_exact():
+    for name, x in _bf16_cases():
+        r = hdc.transform_reduce(x.to(gpu()), {"fn": "identity"}, "exact").item()
+        ref = oracle.reduce({"fn": "identity"}, x)["exact"]
+        assert r == ref, (name, r, ref)
+        # unaligned start: a view that begins one element in
+        if x.numel() > 1:
+            r1 = hdc.transform_reduce(x.to(gpu())[1:], {"fn": "identity"}, "exact").item()
+            assert r1 == oracle.reduce({"fn": "identity"}, x[1:])["exact"], name
+
+
+def test_exact_bf16_sum_independent_of_tuning():
+    x = synth.to_storage(synth.normal_f64(63, 0, (1 << 22) + 3) * torch.exp(
+        10.0 * synth.normal_f64(63, 1, (1 << 22) + 3)), torch.bfloat16)
+    ref = oracle.reduce({"fn": "identity"}, x)["exact"]
+    g = x.to(gpu())
+    b = hdc.tuning_bucket(x.numel())
+    old = hdc.get_tuning(hdc.OP_TRANSFORM_REDUCE, hdc.BF16, hdc.ACC_EXACT, b)
+    try:
+        for block, unroll, gm in [(64, 1, 1), (256, 4, 8), (1024, 8, 64), (128, 2, 3)]:
+            hdc.set_tuning(hdc.OP_TRANSFORM_REDUCE, hdc.BF16, hdc.ACC_EXACT, b, block=block, unroll=unroll,
+                           grid_mult=gm)
+            assert hdc.transform_reduce(g, {"fn": "identity"}, "exact").item() == ref, (block, unroll, gm)
+    finally:
+        hdc.set_tuning(hdc.OP_TRANSFORM_REDUCE, hdc.BF16, hdc.ACC_EXACT, b, **old)
+
+
+def test_exact_bf16_nonfinite():
+    x = torch.zeros(10000, dtype=torch.bfloat16)
+    x[5] = -math.inf
+    assert hdc.transform_reduce(x.to(gpu()), {"fn": "identity"}, "exact").item() == -math.inf
+    x[9000] = math.inf
+    assert math.isnan(hdc.transform_reduce(x.to(gpu()), {"fn": "identity"}, "exact").item())
+    x[9000] = math.nan
+    x[5] = 1.0
+    assert math.isnan(hdc.transform_reduce(x.to(gpu()), {"fn": "identity"}, "exact").item())
+
+
 def horner_of_degree(d, seed=0):
     """Degree-d coefficients with mixed signs and magnitudes (exact in fp32); degree 3 gets a -0.0 top."""
     g = torch.Generator().manual_seed(1000 + d + seed)
