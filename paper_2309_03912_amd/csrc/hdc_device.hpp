@@ -30,16 +30,6 @@ __device__ __forceinline__ Vec<S> load16(const typename S::T* p) {
   return r;
 }
 
-// Cached 16-byte load, for access patterns in which the consecutive loads of
-// a wavefront share cache lines (each lane reading a contiguous run).
-template <class S>
-__device__ __forceinline__ Vec<S> load16_cached(const typename S::T* p) {
-  u32x4 w = *reinterpret_cast<const u32x4*>(p);
-  Vec<S> r;
-  __builtin_memcpy(&r, &w, 16);
-  return r;
-}
-
 // Streaming store that bypasses cache retention (written once, not re-read).
 template <class S>
 __device__ __forceinline__ void store16_nt(typename S::T* p, const Vec<S>& v) {
