@@ -171,9 +171,9 @@ hdc_status hdc_map_reduce(const hdc_functor* f, const hdc_functor* g,
  * hdc_workspace_size(HDC_OP_SCAN, dt, acc, n, 0, ...); calls sharing it must
  * be ordered on one stream.  Two schedules, chosen by the tuning's `unroll`:
  *  - any value but 1 (the default): one pass.  Tiles are handed out in
- *    launch order.  Each tile publishes one node of a binary indexed tree
- *    over the tile totals, and folds its carry from at most log2(tiles)
- *    nodes of earlier tiles, in a fixed order.  The carry between tiles is
+ *    launch order.  Each tile publishes its total as a leaf of a radix-64
+ *    tree (the last tile of a group also the group's node), and folds its
+ *    carry from at most 63 nodes per tree level, in a fixed order.  The carry between tiles is
  *    fp64 for floats and int64 for integers.  x is read once.  A small
  *    clear kernel runs first on the same stream.  The 32-bit word at byte 4
  *    of the workspace is nonzero after the call if a wait for an earlier

@@ -204,8 +204,8 @@ hdc_status launch_batch(const FM& fm, const F& f, const hdc_batch_call* calls, c
 // single pass.  `seg` carries the segment offsets of a segmented scan (Acc a
 // SegAcc), else nothing.  Workspace (scan_workspace_bytes):
 //   three passes: tile sums | tile offsets, one fold state per tile each;
-//   single pass:  256-byte header (ticket, status) | the tiles' tree nodes,
-//                 kWords 8-byte words each.
+//   single pass:  256-byte header (ticket, status) | the tree nodes
+//                 (tree_nodes(G), level by level), kWords 8-byte words each.
 template <class F, class S, class Acc>
 hdc_status launch_scan(const F& f, const void* x, void* y, int64_t n, int exclusive, SegSpec seg, void* ws,
                        const Tuning& t, hipStream_t st) {
@@ -220,7 +220,7 @@ hdc_status launch_scan(const F& f, const void* x, void* y, int64_t n, int exclus
   const dim3 grid((unsigned)G), block(t.block);
   if (t.unroll != 1) {
     uint64_t* w = static_cast<uint64_t*>(ws);
-    const int64_t nwords = 32 + (int64_t)ScanCarry<Acc>::kWords * G;
+    const int64_t nwords = 32 + (int64_t)ScanCarry<Acc>::kWords * tree_nodes(G);
     const ScanLB lb{static_cast<uint32_t*>(ws), static_cast<uint32_t*>(ws) + 1, w + 32};
     const int64_t cb = (nwords + 255) / 256;
     scan_lb_clear_kernel<<<dim3((unsigned)(cb < 1024 ? cb : 1024)), dim3(256), 0, st>>>(w, nwords);

@@ -13,9 +13,10 @@
 //  * three passes, no inter-block waiting -- A: every tile is folded to its
 //    sum; B: one block scans the tile sums into tile offsets; C: every tile
 //    is scanned again and its offset added (x is read twice);
-//  * one pass, tiles handed out in launch order: every tile publishes one
-//    node of a binary indexed tree over the tile totals and folds its carry
-//    from at most log2(tiles) nodes of earlier tiles (x is read once).
+//  * one pass, tiles handed out in launch order: every tile publishes its
+//    total as a leaf of a radix-64 tree (and the last tile of a group the
+//    group's node) and folds its carry from at most 63 nodes per level of
+//    earlier tiles (x is read once).
 // Both are reproducible bit for bit: pass B always folds in one fixed order,
 // and every tree node and carry is a fold in a fixed order of fixed values,
 // whichever tile the timing lets finish first.
@@ -503,15 +504,15 @@ struct ScanCarry<SegAcc<Acc>> {
   __device__ static T unpack(const uint32_t* w) { return {B::unpack(w), w[2]}; }
 };
 
-// Look-back state in the workspace: one tree node per tile, as kWords 64-bit
-// words per tile.  Every word holds one 32-bit part of the value below a
+// Look-back state in the workspace: the tree nodes (tree_nodes(tiles) of
+// them, level by level), kWords 64-bit words each.  Every word holds one 32-bit part of the value below a
 // ready flag (bit 32), so it is written and read by one single-copy-atomic
 // access and no fence orders a value against a separate flag.  All words
 // start at zero (scan_lb_clear_kernel runs first on the same stream).
 struct ScanLB {
   uint32_t* ticket;  // next tile to hand out
   uint32_t* status;  // nonzero: a wait gave up (the result is invalid)
-  uint64_t* node;    // kWords words per tile
+  uint64_t* node;    // level 0 (one node per tile), then levels 1, 2, ...
 };
 
 constexpr uint32_t kLookbackSpinLimit = 1u << 16;  // polls before giving up
@@ -540,81 +541,136 @@ __device__ __forceinline__ bool lb_read(const uint64_t* node, uint32_t (&v)[W]) 
   return ok;
 }
 
-// The carry between tiles as a binary indexed (Fenwick) tree over tile
-// positions i = t + 1.  With L = lowbit(i), tile t publishes
-//   node[t] = fold of tiles (i - L, i - 1]  =  (children, left to right) + A_t,
-// whose children are the nodes of tiles t - 2^m, m = log2 L - 1 .. 0.  Its
-// exclusive carry, the fold of tiles 0 .. t - 1, is the left fold of the
-// nodes on the query path of i - L (increasing) followed by the children.
-// Every term is a node of an earlier tile, at most 31 of them for 2^31
-// tiles, so one lane polls each; the folds are short and in a fixed order,
-// which makes every carry a fixed function of the tile totals: the result
-// does not depend on which tile finished first, and no tile folds more than
-// log2 of the tile count values.  Tiles take their index from a ticket in
-// launch order, so every node waited on belongs to a resident or finished
-// tile and the waits end; the poll count is still bounded, and a give-up
-// marks the status word (the carry is then invalid, but the node is still
-// published so that no other tile waits for it).
-// Run by one whole wavefront; lane 0 publishes node[t].
+// The carry between tiles as a tree of radix 64 over the tile totals.  A
+// level-0 node is one tile's total; the level-(k+1) node j is the fold of the
+// level-k nodes 64 j .. 64 j + 63, i.e. of tiles [64^(k+1) j, 64^(k+1) (j+1)).
+// With t written in base 64 as digits t_k, the exclusive carry of tile t is,
+// for k = K-1 down to 0, the fold of the level-k nodes 64 (t >> 6(k+1)) + e,
+// e < t_k: at most 63 nodes per level, which cover [0, t) left to right, so
+// lane e of one wavefront polls node e of every level at once.  Tile t
+// publishes its level-0 node before it waits; when t is the last tile of a
+// level-(k+1) group (digits 0..k all 63) it also publishes that group's node,
+// = (the 63 level-k terms of its own carry) + its own level-k node, as soon
+// as those terms are in.  A node thus waits for at most k + 1 rounds of polls
+// (K = 3 levels cover 262144 tiles), against log2(tiles) rounds of a binary
+// tree.  Every node and carry is a fold in a fixed order (an ordered
+// wavefront scan) of fixed values: the result does not depend on which tile
+// finished first.  Tiles take their index from a ticket in launch order, so
+// every node waited on belongs to a resident or finished tile and the waits
+// end; the poll count is still bounded, and a give-up marks the status word
+// (the carry is then invalid, but every node this tile owes is published so
+// that no other tile waits for it).
+constexpr int kTreeLevels = 5;  // 64^5 = 2^30 tiles; a launch has fewer than 2^26
+
+__host__ __device__ constexpr int tree_levels(int64_t tiles) {
+  int K = 1;
+  while (K < kTreeLevels && ((int64_t)1 << (6 * K)) < tiles) ++K;
+  return K;
+}
+
+// Nodes of all levels for `tiles` tiles (level k holds ceil(tiles / 64^k)).
+__host__ __device__ constexpr int64_t tree_nodes(int64_t tiles) {
+  int64_t sum = 0, cnt = tiles;
+  for (int k = 0; k < tree_levels(tiles); ++k) {
+    sum += cnt;
+    cnt = (cnt + 63) >> 6;
+  }
+  return sum;
+}
+
+// Ordered fold of the values of lanes 0 .. m-1 (m >= 1, uniform), in lane
+// order, returned in every lane.  Lane l's value is in words
+// slot[i * 64 + l], i < kWords (LDS).
 template <class C>
-__device__ typename C::T scan_tree_carry(const ScanLB& lb, int64_t t, typename C::T own) {
+__device__ __forceinline__ typename C::T wave_ordered_fold(const uint32_t* slot, int m) {
   constexpr int W = C::kWords;
   const int lane = threadIdx.x & 63;
-  const uint64_t i = (uint64_t)t + 1;
-  const uint64_t L = i & (~i + 1);
-  const int s = __builtin_ctzll(L);             // children
-  const uint64_t base = i - L;                  // query position
-  const int r = __builtin_popcountll(base);     // query nodes
-  int64_t dep = -1;                             // this lane's node: entry `lane`
-  if (lane < r) {
-    uint64_t p = base;
-    for (int k = 0; k < r - 1 - lane; ++k) p &= p - 1;  // clear the lowest set bits
-    dep = (int64_t)p - 1;
-  } else if (lane < r + s) {
-    dep = t - ((int64_t)1 << (s - 1 - (lane - r)));
-  }
-  bool ready = dep < 0;
-  uint32_t val[W] = {};
-  auto entry = [&](int e) {  // the value lane e read, in every lane
-    uint32_t w[W];
+  uint32_t w[W];
 #pragma unroll
-    for (int k = 0; k < W; ++k) w[k] = (uint32_t)__builtin_amdgcn_readlane((int)val[k], e);
-    return C::unpack(w);
+  for (int k = 0; k < W; ++k) w[k] = slot[k * 64 + lane];
+  typename C::T x = C::unpack(w);
+  for (int d = 1; d < m; d <<= 1) {
+    uint32_t u[W];
+    C::pack(x, w);
+#pragma unroll
+    for (int k = 0; k < W; ++k) u[k] = (uint32_t)__shfl_up((int)w[k], d, 64);
+    const typename C::T lower = C::unpack(u);
+    if (lane >= d) x = C::add(lower, x);
+  }
+  uint32_t r[W];
+  C::pack(x, w);
+#pragma unroll
+  for (int k = 0; k < W; ++k) r[k] = (uint32_t)__builtin_amdgcn_readlane((int)w[k], m - 1);
+  return C::unpack(r);
+}
+
+// Run by one whole wavefront; lane 0 publishes.  `tiles` is the grid size;
+// `slots` (LDS, kTreeLevels * kWords * 64 words) keeps the polled values.
+template <class C>
+__device__ typename C::T scan_tree_carry(const ScanLB& lb, int64_t t, int64_t tiles, typename C::T own,
+                                         uint32_t* slots) {
+  constexpr int W = C::kWords;
+  using T = typename C::T;
+  const int lane = threadIdx.x & 63;
+  const int K = tree_levels(tiles);
+  // Level k starts at word start(k); node j of level k is at start(k) + W j.
+  auto start = [&](int k) {
+    int64_t off = 0, cnt = tiles;
+    for (int j = 0; j < k; ++j) {
+      off += (int64_t)W * cnt;
+      cnt = (cnt + 63) >> 6;
+    }
+    return off;
   };
-  auto publish = [&](typename C::T x) {
+  auto digit = [&](int k) { return (int)((t >> (6 * k)) & 63); };
+  auto publish = [&](int k, T x) {
     uint32_t w[W];
     C::pack(x, w);
-    lb_publish<W>(lb.node + (int64_t)W * t, w);
+    if (lane == 0) lb_publish<W>(lb.node + start(k) + (int64_t)W * (t >> (6 * k)), w);
   };
-  bool published = false, all = false;
-  const bool is_child = lane >= r && lane < r + s;
+  publish(0, own);
+  int P = 0;  // group nodes this tile owes: levels 1 .. P
+  while (P < K - 1 && digit(P) == 63) ++P;
+  uint32_t pend = 0;  // bit k: this lane still waits for its level-k node
+  for (int k = 0; k < K; ++k)
+    if (lane < digit(k)) pend |= 1u << k;
+  T up = own;  // this tile's node at level `pub`
+  int pub = 0;
+  bool all = false;
   for (uint32_t polls = 0;; ++polls) {
-    if (!ready) ready = lb_read<W>(lb.node + (int64_t)W * dep, val);
-    if (!published && __builtin_amdgcn_ballot_w64(is_child && !ready) == 0) {
-      typename C::T x = own;
-      if (s > 0) {
-        x = entry(r);
-        for (int e = r + 1; e < r + s; ++e) x = C::add(x, entry(e));
-        x = C::add(x, own);
+    for (int k = 0; k < K; ++k) {
+      if ((pend >> k) & 1u) {
+        uint32_t v[W];
+        const int64_t j = ((t >> (6 * (k + 1))) << 6) + lane;
+        if (lb_read<W>(lb.node + start(k) + (int64_t)W * j, v)) {
+#pragma unroll
+          for (int i = 0; i < W; ++i) slots[(k * W + i) * 64 + lane] = v[i];
+          pend &= ~(1u << k);
+        }
       }
-      if (lane == 0) publish(x);
-      published = true;
     }
-    all = __builtin_amdgcn_ballot_w64(!ready) == 0;
+    for (; pub < P; ++pub) {
+      if (__builtin_amdgcn_ballot_w64((pend >> pub) & 1u) != 0) break;
+      up = C::add(wave_ordered_fold<C>(slots + pub * W * 64, 63), up);
+      publish(pub + 1, up);
+    }
+    all = __builtin_amdgcn_ballot_w64(pend != 0) == 0;
     if (all || polls >= kLookbackSpinLimit) break;
     __builtin_amdgcn_s_sleep(1);
   }
   if (!all) {  // gave up: keep the others moving, flag the result
-    if (lane == 0) {
-      if (!published) publish(own);
-      __hip_atomic_store(lb.status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    for (; pub < P; ++pub) publish(pub + 1, own);
+    if (lane == 0) __hip_atomic_store(lb.status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return C::zero();
   }
-  typename C::T carry = C::zero();
-  if (r + s > 0) {
-    carry = entry(0);
-    for (int e = 1; e < r + s; ++e) carry = C::add(carry, entry(e));
+  T carry = C::zero();
+  bool any = false;
+  for (int k = K - 1; k >= 0; --k) {
+    const int m = digit(k);
+    if (m == 0) continue;
+    const T f = wave_ordered_fold<C>(slots + k * W * 64, m);
+    carry = any ? C::add(carry, f) : f;
+    any = true;
   }
   return carry;
 }
@@ -628,6 +684,7 @@ __global__ __launch_bounds__(1024) void scan_onepass_kernel(F f, const elem_t<S>
   __shared__ Acc lds[kMaxWaves];
   __shared__ int64_t tile_sh;
   __shared__ typename C::T carry_sh;
+  __shared__ uint32_t slots[kTreeLevels * C::kWords * 64];
   if (threadIdx.x == 0) tile_sh = (int64_t)atomicAdd(lb.ticket, 1u);
   __syncthreads();
   const int64_t tile = tile_sh;
@@ -637,7 +694,7 @@ __global__ __launch_bounds__(1024) void scan_onepass_kernel(F f, const elem_t<S>
   Acc total;
   const Acc before = block_wave_prefix(w.wave_total, lds, &total);
   if (threadIdx.x < 64) {
-    const typename C::T carry = scan_tree_carry<C>(lb, tile, C::of(total));
+    const typename C::T carry = scan_tree_carry<C>(lb, tile, (int64_t)gridDim.x, C::of(total), slots);
     if (threadIdx.x == 0) carry_sh = carry;
   }
   __syncthreads();

@@ -101,9 +101,10 @@ def test_scan_large_sampled():
 
 @pytest.mark.parametrize("block", [64, 256, 1024])
 def test_scan_many_tiles_and_status(block, schedule):
-    """Thousands of tiles (the look-back crosses windows of 64 predecessors), every output checked."""
+    """Thousands of tiles, every output checked.  At block 64 there are 4101 tiles: the carry tree has three
+    levels (groups of 64 and of 4096 tiles) and the last tile is a partial one."""
     set_scan_tuning(4 if schedule == "single_pass" else 1, block=block)
-    n = 64 * 16 * 3000 + 123 if block == 64 else (1 << 22) + 5
+    n = 64 * 16 * 4100 + 123 if block == 64 else (1 << 22) + 5
     x = synth.uniform_pm1_f32(11, 0, n)
     ws = hdc.workspace(gpu(), hdc.OP_SCAN, hdc.F32, hdc.ACC_COMPENSATED, n)
     y = hdc.scan(x.to(gpu()), FNS["horner"], "compensated", ws=ws)

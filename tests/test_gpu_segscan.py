@@ -141,3 +141,30 @@ def test_segscan_lognormal_full_size_sampled():
             assert abs(float(y[i]) - r["exact"]) <= 1e-6 * r["abs_sum"], (j, i)
     del xg
     torch.cuda.empty_cache()
+
+
+def test_segscan_many_small_tiles(schedule):
+    """Block 64: 4101 tiles, so the single pass's carry tree has three levels (groups of 64 and of 4096
+    tiles) and its nodes carry the segment-start flag; every position checked."""
+    saved = {(dt, acc): hdc.get_tuning(hdc.OP_SCAN, dt, acc, 3) for dt, acc in CLASSES}
+    try:
+        for dt, acc in CLASSES:
+            hdc.set_tuning(hdc.OP_SCAN, dt, acc, -1, block=64)
+        rng = np.random.default_rng(7)
+        L = torch.tensor(rng.integers(0, 2000, 4200).tolist(), dtype=torch.int64)
+        off = synth.offsets_from_lengths(L)
+        total = 64 * 16 * 4100 + 123
+        off = torch.clamp(off, max=total)
+        n = total
+        assert (n + 1023) // 1024 == 4101
+        mask = inside(off, n)
+        x = synth.uniform_pm1_f32(14, 0, n)
+        y = hdc.segmented_scan(x.to(gpu()), off.to(gpu()), HOR, "compensated")
+        check_float(y, oracle.segmented_scan(HOR, x, off), mask, "f32 compensated, block 64")
+        xi = synth.uniform_int(15, 10, n)
+        yi = hdc.segmented_scan(xi.to(gpu()), off.to(gpu()), IAFF, "exact_int", exclusive=True)
+        ref = oracle.segmented_scan(IAFF, xi, off, True)["isum"]
+        assert np.array_equal(yi.cpu().numpy()[mask], ref[mask])
+    finally:
+        for (dt, acc), t in saved.items():
+            hdc.set_tuning(hdc.OP_SCAN, dt, acc, -1, **t)
