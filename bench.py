@@ -224,7 +224,10 @@ def form_precision(args, torch, hdc, synth):
         x = synth.to_storage(xg64, dt)
         z = synth.to_storage(zg64, dt)
         v, info = synth.ill_conditioned(seed, n, dt, device=dev)
+        # an ill-conditioned dot: products x2 * z2 are exactly the values v
+        x2, z2, info2 = synth.ill_conditioned_dot(seed, n, dt, device=dev)
         xf, zf, vf = x.float(), z.float(), v.float()  # the plain-FP32 comparator reads widened copies
+        x2f, z2f = x2.float(), z2.float()
         ident, prod = hdc.identity(), hdc.product()
         runs = {
             "sum_x": (lambda: hdc.transform_reduce(x, ident, "compensated"), 2 * n,
@@ -233,8 +236,11 @@ def form_precision(args, torch, hdc, synth):
                        lambda: hdc.transform_reduce(xf, prod, "plain", z=zf), 8 * n),
             "sum_v_kappa": (lambda: hdc.transform_reduce(v, ident, "compensated"), 2 * n,
                             lambda: hdc.transform_reduce(vf, ident, "plain"), 4 * n),
+            "dot_kappa": (lambda: hdc.transform_reduce(x2, prod, "compensated", z=z2), 4 * n,
+                          lambda: hdc.transform_reduce(x2f, prod, "plain", z=z2f), 8 * n),
         }
-        res = {"kappa": info["kappa"]}
+        res = {"kappa": info["kappa"], "dot_kappa_kappa": info2["kappa"]}
+        refs = {}
         for op, (fc, bc, fp, bp) in runs.items():
             tc = ev_time(torch, fc)
             tp = ev_time(torch, fp)
@@ -246,25 +252,30 @@ def form_precision(args, torch, hdc, synth):
                 import oracle
                 if op == "sum_v_kappa":
                     ref = {"exact": info["target"], "abs_sum": info["abs_sum"], "seq64": float("nan")}
+                elif op == "dot_kappa":
+                    ref = {"exact": info2["target"], "abs_sum": info2["abs_sum"], "seq64": float("nan")}
                 elif op == "sum_x":
                     ref = oracle.reduce(ident, x)
                 else:
                     ref = oracle.reduce(prod, x, z)
+                refs[op] = ref["exact"]
                 entry["comp_err"] = err_fields(rc, ref)
                 entry["plain_f32_err"] = err_fields(rp, ref)
             res[op] = entry
-        # exact 16-bit sums: the correctly rounded exact sum, independent of order and tuning
-        for op, arr in (("sum_x", x), ("sum_v_kappa", v)):
-            fe = lambda: hdc.transform_reduce(arr, ident, "exact")
+        # exact sums (and fp16 dots): the correctly rounded exact result, independent of order and tuning
+        exact_runs = [("sum_x", lambda: hdc.transform_reduce(x, ident, "exact"), 2 * n),
+                      ("sum_v_kappa", lambda: hdc.transform_reduce(v, ident, "exact"), 2 * n)]
+        if dt == torch.float16:
+            exact_runs += [("dot_xz", lambda: hdc.transform_reduce(x, prod, "exact", z=z), 4 * n),
+                           ("dot_kappa", lambda: hdc.transform_reduce(x2, prod, "exact", z=z2), 4 * n)]
+        for op, fe, be in exact_runs:
             te = ev_time(torch, fe)
-            entry = {"exact_ms": round(te, 5), "exact_GBps": round(gbps(2 * n, te), 1)}
+            entry = {"exact_ms": round(te, 5), "exact_GBps": round(gbps(be, te), 1)}
             if not args.no_check:
-                import oracle
-                exact = info["target"] if op == "sum_v_kappa" else oracle.reduce(ident, x)["exact"]
-                entry["exact_bits_equal_oracle"] = fe().item() == exact
+                entry["exact_bits_equal_oracle"] = fe().item() == refs[op]
             res[op].update(entry)
         out[name] = res
-        del x, z, v, xf, zf, vf
+        del x, z, v, xf, zf, vf, x2, z2, x2f, z2f
         torch.cuda.empty_cache()
     return out
 

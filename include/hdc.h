@@ -79,12 +79,15 @@ typedef enum hdc_accum {
                               final cross-block combine; `out` is one double */
   HDC_ACC_EXACT_INT = 2,   /* int32: int64 sums wrapping mod 2^64; `out` is
                               one int64 */
-  HDC_ACC_EXACT = 3        /* fp16 or bf16 storage, IDENTITY fold: the
-                              exact real sum rounded once to fp64
+  HDC_ACC_EXACT = 3        /* the exact real sum rounded once to fp64
                               (nearest-even); `out` is one double.
                               Independent of order and tuning:
-                              bit-reproducible.  transform_reduce (fp16 and
-                              bf16) and map_reduce (fp16) only. */
+                              bit-reproducible.  IDENTITY folds of fp16 or
+                              bf16 storage (transform_reduce; map_reduce for
+                              fp16) and PRODUCT folds (dot products) of fp16
+                              storage with n < 2^31.  A non-finite term
+                              makes the result its IEEE sum of the
+                              non-finite terms (inf * 0 is NaN). */
 } hdc_accum;
 
 typedef enum hdc_op {

@@ -231,7 +231,7 @@ def map(x: torch.Tensor, fn, out: torch.Tensor | None = None) -> torch.Tensor:
 def transform_reduce(x: torch.Tensor, fn, acc="plain", z: torch.Tensor | None = None,
                      out: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
     """sum_i fn(x[i]) (or sum_i x[i]*z[i] for product()) as a 0-d device tensor:
-    float32 (plain), float64 (compensated) or int64 (exact_int)."""
+    float32 (plain), float64 (compensated, exact) or int64 (exact_int)."""
     x = _gpu_tensor(x, "x")
     a = _acc(acc)
     dt = _dtype(x)

@@ -237,6 +237,7 @@ def default_cases(dev, quick=False, log2n=28):
         Case(OP_DOT, F32, ACC_PLAIN, n, dev),
         Case(OP_DOT, BF16, ACC_COMPENSATED, n, dev),
         Case(OP_DOT, F16, ACC_COMPENSATED, n, dev),
+        Case(OP_DOT, F16, ACC_EXACT, n, dev),
     ]
     L = synth.segment_lengths(synth.seed_of(4))
     off = synth.offsets_from_lengths(L)

@@ -282,8 +282,10 @@ static hdc_status reduce_common(const hdc_functor* f, const hdc_functor* fm, hdc
   HDC_TRY(check_functor(f, dt, !fused));
   if (fused) HDC_TRY(check_functor(fm, dt, false));
   HDC_TRY(check_acc(dt, acc));
-  if (acc == HDC_ACC_EXACT && f->id != HDC_FN_IDENTITY)
-    return fail(HDC_ERR_UNSUPPORTED, "EXACT folds the IDENTITY callable only");
+  if (acc == HDC_ACC_EXACT && f->id != HDC_FN_IDENTITY && !(f->id == HDC_FN_PRODUCT && dt == HDC_F16 && !fused))
+    return fail(HDC_ERR_UNSUPPORTED, "EXACT folds IDENTITY (fp16, bf16) and PRODUCT (fp16) only");
+  if (acc == HDC_ACC_EXACT && f->id == HDC_FN_PRODUCT && n >= (int64_t(1) << 31))
+    return fail(HDC_ERR_UNSUPPORTED, "EXACT dot products take fewer than 2^31 terms");
   if (acc == HDC_ACC_EXACT && fused && dt != HDC_F16)
     return fail(HDC_ERR_UNSUPPORTED, "EXACT map_reduce is provided for fp16 storage");
   if (n < 0) return fail(HDC_ERR_INVALID_ARGUMENT, "n = %lld is negative", (long long)n);

@@ -100,6 +100,34 @@ inline hdc_status launch_exact_bf16(const void* x, int64_t n, void* out, void* w
   return check_launch("exact bf16 final launch");
 }
 
+// Exact fp16 dot product: vectors when x and z share their 16-byte offset,
+// else one element at a time.
+inline hdc_status launch_exact_f16_dot(const void* x, const void* z, int64_t n, void* out, void* ws,
+                                       const Tuning& t, hipStream_t st) {
+  int cus = 0;
+  HDC_TRY(compute_units(&cus));
+  const bool vec = ((uintptr_t)x % 16) == ((uintptr_t)z % 16);
+  const Range r = make_range<F16>(x, n, vec);
+  const int u = !vec ? 1 : t.unroll >= 4 ? 4 : t.unroll;
+  int64_t g = grid_for(vec ? r.nvec : n, (int64_t)t.block * u, cus, t);
+  if (g > 4096) g = 4096;
+  F16DotExact* partials = static_cast<F16DotExact*>(ws);
+  const uint16_t* xp = static_cast<const uint16_t*>(x);
+  const uint16_t* zp = static_cast<const uint16_t*>(z);
+  const dim3 grid((unsigned)g), block(t.block);
+  if (!vec)
+    exact_f16_dot_kernel<1, false><<<grid, block, 0, st>>>(xp, zp, r, partials);
+  else if (u == 1)
+    exact_f16_dot_kernel<1, true><<<grid, block, 0, st>>>(xp, zp, r, partials);
+  else if (u == 2)
+    exact_f16_dot_kernel<2, true><<<grid, block, 0, st>>>(xp, zp, r, partials);
+  else
+    exact_f16_dot_kernel<4, true><<<grid, block, 0, st>>>(xp, zp, r, partials);
+  HDC_TRY(check_launch("exact fp16 dot launch"));
+  exact_f16_dot_final_kernel<<<dim3(1), dim3(256), 0, st>>>(partials, (int)g, static_cast<double*>(out));
+  return check_launch("exact fp16 dot final launch");
+}
+
 template <class F, class S, class Acc>
 hdc_status launch_segmented(const F& f, const void* x, const int64_t* off, int64_t nseg, int64_t total, void* out,
                             void* ws, const Tuning& t, hipStream_t st) {

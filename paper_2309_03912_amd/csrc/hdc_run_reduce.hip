@@ -7,7 +7,8 @@ hdc_status run_reduce(const hdc_functor& f, hdc_dtype dt, const void* x, const v
                       void* out, void* ws, const Tuning& t, hipStream_t st) {
   if (dt == HDC_I32)
     return with_int_fn(f, [&](auto fn) { return launch_reduce<decltype(fn), I32, IntAcc>(fn, x, z, n, out, ws, t, st); });
-  if (acc == HDC_ACC_EXACT) {  // checked on entry: IDENTITY on F16 or BF16 storage
+  if (acc == HDC_ACC_EXACT) {  // checked on entry: IDENTITY on F16 or BF16 storage, PRODUCT on F16
+    if (f.id == HDC_FN_PRODUCT) return launch_exact_f16_dot(x, z, n, out, ws, t, st);
     if (dt == HDC_BF16) return launch_exact_bf16(x, n, out, ws, t, st);
     return launch_reduce<Identity, F16, ExactAcc>(Identity{}, x, z, n, out, ws, t, st);
   }

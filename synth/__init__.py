@@ -52,6 +52,7 @@ STREAM = {
     "force": 8,        # index of the segment forced to the maximum length
     "xn": 9,           # normal first operand of the fp32 dot
     "xi": 10,          # integer operand
+    "dot_scale": 11,   # signs and power-of-two splits of the ill-conditioned dot
 }
 
 
@@ -308,6 +309,29 @@ def ill_conditioned(seed: int, n: int, dtype: torch.dtype, kappa: float = 1e8,
         "slots_used": len(fill),
     }
     return v, info
+
+
+def ill_conditioned_dot(seed: int, n: int, dtype: torch.dtype, kappa: float = 1e8, device="cpu"):
+    """Operands x, z of a dot product whose products are exactly the ill-conditioned
+    values v of ``ill_conditioned`` (so the exact dot is its target and its condition
+    number is the same): z_i = s_i 2^k_i with a seeded sign s_i and k_i in [-2, 2],
+    x_i = s_i v_i 2^-k_i; where that x_i is not representable, k_i = 0.
+
+    Returns (x, z, info) with info as for ``ill_conditioned``.
+    """
+    v, info = ill_conditioned(seed, n, dtype, kappa, device=device)
+    w = u64(seed, STREAM["dot_scale"], 0, n, device)
+    k = ((_lsr(w, 32) * 5) >> 32).to(torch.float64) - 2.0     # uniform in {-2, ..., 2}
+    s = 1.0 - 2.0 * (_lsr(w, 31) & 1).to(torch.float64)
+    del w
+    v64 = v.to(torch.float64)
+    x64 = s * v64 * torch.exp2(-k)
+    x = to_storage(x64, dtype)
+    ok = x.to(torch.float64) == x64
+    k = torch.where(ok, k, torch.zeros_like(k))
+    x = torch.where(ok, x, to_storage(s * v64, dtype))
+    z = (s * torch.exp2(k)).to(dtype)
+    return x, z, info
 
 
 # ---------------------------------------------------------------------------

@@ -91,6 +91,12 @@ def test_transform_reduce_rejects_bad_arguments():
     assert L.hdc_transform_reduce(*args(acc=hdc.ACC_EXACT)) == hdc.ERR_UNSUPPORTED            # exact: 16-bit only
     assert L.hdc_transform_reduce(*args(acc=hdc.ACC_EXACT, dt=hdc.F16,
                                         f=fn({"fn": "horner", "coef": [1.0]}))) == hdc.ERR_UNSUPPORTED
+    prod = fn({"fn": "product"})
+    assert L.hdc_transform_reduce(*args(acc=hdc.ACC_EXACT, dt=hdc.BF16, f=prod, z=FAKE)) == hdc.ERR_UNSUPPORTED
+    assert "PRODUCT (fp16)" in last()                                                   # exact dot: fp16 only
+    assert L.hdc_transform_reduce(*args(acc=hdc.ACC_EXACT, dt=hdc.F16, f=prod, z=FAKE,
+                                        n=1 << 31)) == hdc.ERR_UNSUPPORTED
+    assert "2^31" in last()
     assert L.hdc_transform_reduce(*args(wsb=need - 1)) == hdc.ERR_WORKSPACE
     assert "smaller" in last()
     assert L.hdc_transform_reduce(*args(ws=FAKE + 8)) == hdc.ERR_INVALID_ARGUMENT

@@ -407,3 +407,82 @@ def test_horner_every_degree(degree):
         x16 = make_x(n, torch.float16, seed=degree + 2)
         y16 = hdc.map(x16.to(gpu()), fn)
         assert torch.equal(bits(y16.cpu()), bits(oracle.map(fn, x16))), (degree, n, "f16")
+
+
+# --------------------------------------------------------------------------
+# exact fp16 dot products: 16-bit digits over the whole product range
+# --------------------------------------------------------------------------
+
+def _fp16_dot_cases():
+    n = (1 << 20) + 5
+    yield "normal", (synth.to_storage(synth.normal_f64(81, 0, n), torch.float16),
+                     synth.to_storage(synth.normal_f64(81, 1, n), torch.float16))
+    wide = lambda s, k: synth.to_storage(synth.normal_f64(s, k, 300007) * torch.exp(
+        3.0 * synth.normal_f64(s, k + 2, 300007)), torch.float16)  # subnormals to 65504
+    yield "wide", (wide(82, 0), wide(82, 1))
+    x, z, _ = synth.ill_conditioned_dot(synth.seed_of(3), 1 << 20, torch.float16)
+    yield "kappa1e8", (x, z)
+    ext = torch.tensor([65504.0, -65504.0, 2.0 ** -24, -(2.0 ** -24), 0.0, -0.0, 1.0, 3.0], dtype=torch.float16)
+    yield "extremes", (ext, torch.tensor([65504.0, 65504.0, 2.0 ** -24, 2.0 ** -24, 5.0, 7.0, -1.0, 2.0 ** -14],
+                                         dtype=torch.float16))
+    yield "max_products", (torch.full((70001,), 65504.0, dtype=torch.float16),
+                           torch.full((70001,), -65504.0, dtype=torch.float16))
+    for m in (0, 1, 7, 8, 9, 4097):
+        yield f"n{m}", (synth.to_storage(synth.uniform_pm1_f32(m + 90, 0, m).double() * 300, torch.float16),
+                        synth.to_storage(synth.uniform_pm1_f32(m + 90, 1, m).double() * 300, torch.float16))
+
+
+def test_exact_fp16_dot_is_bit_exact():
+    for name, (x, z) in _fp16_dot_cases():
+        gx, gz = x.to(gpu()), z.to(gpu())
+        r = hdc.transform_reduce(gx, {"fn": "product"}, "exact", z=gz).item()
+        ref = oracle.reduce({"fn": "product"}, x, z)["exact"]
+        assert r == ref, (name, r, ref)
+        if x.numel() > 2:
+            # both one element in (vector body with a head), and x one in against z two in (element path)
+            r1 = hdc.transform_reduce(gx[1:], {"fn": "product"}, "exact", z=gz[1:]).item()
+            assert r1 == oracle.reduce({"fn": "product"}, x[1:], z[1:])["exact"], name
+            r2 = hdc.transform_reduce(gx[1:-1], {"fn": "product"}, "exact", z=gz[2:]).item()
+            assert r2 == oracle.reduce({"fn": "product"}, x[1:-1], z[2:])["exact"], name
+
+
+def test_exact_fp16_dot_ill_conditioned_equals_target():
+    x, z, info = synth.ill_conditioned_dot(synth.seed_of(3), 1 << 22, torch.float16)
+    assert info["kappa"] > 1e7
+    r = hdc.transform_reduce(x.to(gpu()), {"fn": "product"}, "exact", z=z.to(gpu())).item()
+    assert r == info["target"]
+
+
+def test_exact_fp16_dot_independent_of_tuning():
+    n = (1 << 22) + 3
+    x = synth.to_storage(synth.normal_f64(83, 0, n) * 50, torch.float16)
+    z = synth.to_storage(synth.normal_f64(83, 1, n) * 50, torch.float16)
+    ref = oracle.reduce({"fn": "product"}, x, z)["exact"]
+    gx, gz = x.to(gpu()), z.to(gpu())
+    b = hdc.tuning_bucket(n)
+    old = hdc.get_tuning(hdc.OP_DOT, hdc.F16, hdc.ACC_EXACT, b)
+    try:
+        for block, unroll, gm in [(64, 1, 1), (256, 4, 8), (1024, 8, 64), (128, 2, 3)]:
+            hdc.set_tuning(hdc.OP_DOT, hdc.F16, hdc.ACC_EXACT, b, block=block, unroll=unroll, grid_mult=gm)
+            assert hdc.transform_reduce(gx, {"fn": "product"}, "exact", z=gz).item() == ref, (block, unroll, gm)
+    finally:
+        hdc.set_tuning(hdc.OP_DOT, hdc.F16, hdc.ACC_EXACT, b, **old)
+
+
+def test_exact_fp16_dot_nonfinite():
+    x = torch.ones(10000, dtype=torch.float16)
+    z = torch.ones(10000, dtype=torch.float16)
+    dot = lambda: hdc.transform_reduce(x.to(gpu()), {"fn": "product"}, "exact", z=z.to(gpu())).item()
+    x[5] = math.inf
+    assert dot() == math.inf
+    z[5] = -2.0
+    assert dot() == -math.inf
+    z[5] = 0.0                      # inf * 0
+    assert math.isnan(dot())
+    z[5] = 1.0
+    x[9000] = -math.inf             # inf + -inf
+    z[9000] = 1.0
+    assert math.isnan(dot())
+    x[9000] = 1.0
+    x[77] = math.nan
+    assert math.isnan(dot())

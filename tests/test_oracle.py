@@ -306,6 +306,31 @@ def test_dot_is_exact_products():
     assert oracle.reduce({"fn": "product"}, z, x)["exact"] == r["exact"]
 
 
+def test_dot_f16_exact_over_the_whole_range():
+    # fp16 x fp16 products are exact in fp32 (<= 22 significant bits); over the whole
+    # fp16 range (65504^2 down to 2^-48) the exact dot is the Fraction sum, rounded once.
+    rng = np.random.default_rng(3)
+    bits = rng.integers(0, 1 << 16, 6000, dtype=np.int64)
+    bits = bits[((bits >> 10) & 31) != 31]            # finite values only
+    x = torch.from_numpy(bits[:2500].astype(np.int16)).view(torch.float16)
+    z = torch.from_numpy(bits[2500:5000].astype(np.int16)).view(torch.float16)
+    special = torch.tensor([65504.0, -65504.0, 2.0 ** -24, -(2.0 ** -24), 0.0, -0.0, 1.0], dtype=torch.float16)
+    x = torch.cat([x, special, special])
+    z = torch.cat([z, special, special.flip(0)])
+    r = oracle.reduce({"fn": "product"}, x, z)
+    exact = sum(Fraction(a) * Fraction(b) for a, b in zip(x.double().tolist(), z.double().tolist()))
+    assert r["exact"] == float(exact)
+    A = float(sum(abs(Fraction(a) * Fraction(b)) for a, b in zip(x.double().tolist(), z.double().tolist())))
+    assert abs(r["abs_sum"] - A) <= 1e-12 * A  # the tolerance denominator is a plain fp64 sum
+
+
+def test_dot_f16_ill_conditioned_target():
+    # x * z == v exactly for the ill-conditioned construction: the exact dot is its target
+    x, z, info = synth.ill_conditioned_dot(7, 1 << 14, torch.float16, kappa=1e6)
+    assert torch.equal(x.double() * z.double(), synth.ill_conditioned(7, 1 << 14, torch.float16, kappa=1e6)[0].double())
+    assert oracle.reduce({"fn": "product"}, x, z)["exact"] == info["target"]
+
+
 def test_reduce_equals_fsum_of_mapped_terms():
     x = synth.uniform_pm1_f32(1, 0, 20000)
     terms = oracle.map(HORNER, x).double().tolist()
