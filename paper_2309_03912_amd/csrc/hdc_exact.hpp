@@ -174,6 +174,14 @@ __global__ __launch_bounds__(1024) void exact_bf16_kernel(const uint16_t* __rest
       }
       fold(tm);
     }
+    // Carry digits 0..6 up once per step, so that they stay far below 2^63
+    // however many steps a lane takes; digit 7 only takes values >= 2^91.
+#pragma unroll
+    for (int j = 0; j + 1 < kExactFoldDigits; ++j) {
+      const int64_t cy = acc[j] >> 32;
+      acc[j] -= cy * (int64_t(1) << 32);
+      acc[j + 1] += cy;
+    }
   }
   if (blockIdx.x == gridDim.x - 1) {  // unaligned head and the tail, one element per lane
     Bf16Term tm[V];
