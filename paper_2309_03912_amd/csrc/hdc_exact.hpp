@@ -210,80 +210,72 @@ static __global__ __launch_bounds__(256) void exact_bf16_final_kernel(const Bf16
 }
 
 // ---------------------------------------------------------------------------
-// Exact dot product of fp16 vectors.  A finite fp16 value is m 2^(q - 24)
-// with an integer m < 2^11 and q in [0, 29], so a product is M 2^(Q - 48)
-// with M = m_x m_z < 2^22 and Q = q_x + q_z in [0, 58]: the integer
-// M << (Q mod 16) < 2^37 added to digit Q / 16 (0..3) of a fixed-point number
-// whose digit j has the unit 2^(16 j - 48).  Lanes keep the four digits in
-// int64 registers (carry-save) and carry them up once per grid-stride step;
-// the total, below 2^63 in magnitude for fewer than 2^31 products, is the
-// 128-bit integer sum_j d_j 2^(16 j) in units of 2^-48, rounded once to fp64.
-// A product with an infinite or NaN factor is tracked as a flag with its IEEE
-// value (inf * 0 is NaN), and their sum as for the bf16 sums.
+// Exact dot product of fp16 vectors.  The product p of two fp16 values is
+// exact in fp32 (at most 22 significant bits, 2^-48 <= |p| < 2^32 unless 0)
+// and is an integer multiple of 2^-48.  Split at 2^-8, p = h + l with
+// h = trunc(p 2^8) 2^-8 (a multiple of 2^-8 below 2^32) and l = p - h (a
+// multiple of 2^-48 below 2^-8); both steps are exact in fp32.  Each part
+// spans at most 40 bits, so fp64 chains of up to 2^13 of them never round.
+// Lanes flush their two chains once per grid-stride step into a 128-bit
+// two's-complement integer in units of 2^-48 (h 2^8 and l 2^48 are integers
+// below 2^53); the total, below 2^63 in magnitude for fewer than 2^31
+// products, is rounded once to fp64.  A product with an infinite or NaN
+// factor (inf * 0 is NaN) goes to the high chain only, and the non-finite
+// chain values add by IEEE rules in `nf`.
 // ---------------------------------------------------------------------------
 
-constexpr int kDotDigits = 4;
-
 struct F16DotExact {
-  int64_t d[kDotDigits];
-  uint32_t nf;  // bit 0: +inf, bit 1: -inf, bit 2: NaN
+  double dh;  // chain of high parts
+  double dl;  // chain of low parts
+  float nf;   // IEEE sum of the non-finite chains; 0 if none
   uint32_t pad;
-  __device__ static F16DotExact zero() { return {{0, 0, 0, 0}, 0u, 0u}; }
-  __device__ static F16DotExact merge(F16DotExact a, const F16DotExact& b) {
-#pragma unroll
-    for (int j = 0; j < kDotDigits; ++j) a.d[j] += b.d[j];
-    a.nf |= b.nf;
+  uint64_t lo, hi;  // 128-bit two's complement, units of 2^-48
+  __device__ static F16DotExact zero() { return {0.0, 0.0, 0.0f, 0u, 0u, 0u}; }
+  __device__ void add(float p) {
+    const float h = __builtin_truncf(p * 256.0f) * 0.00390625f;
+    const float l = __builtin_isfinite(p) ? p - h : 0.0f;
+    dh += (double)h;
+    dl += (double)l;
+  }
+  __device__ void add128(uint64_t low, uint64_t high) {
+    const uint64_t s = lo + low;
+    hi += high + (s < lo ? 1u : 0u);
+    lo = s;
+  }
+  __device__ void flush() {
+    if (!__builtin_isfinite(dh)) {
+      nf += (float)dh;
+    } else {
+      const int64_t qh = (int64_t)(dh * 256.0);                // |.| < 2^53: exact
+      const int64_t ql = (int64_t)(dl * 281474976710656.0);    // 2^48; |.| < 2^53: exact
+      add128((uint64_t)ql, (uint64_t)(ql >> 63));
+      add128((uint64_t)qh << 40, (uint64_t)(qh >> 24));     // qh 2^40 as 128 bits
+    }
+    dh = 0.0;
+    dl = 0.0;
+  }
+  __device__ static F16DotExact merge(F16DotExact a, F16DotExact b) {
+    a.flush();
+    b.flush();
+    a.nf += b.nf;
+    a.add128(b.lo, b.hi);
     return a;
   }
-  // Digits 0..2 end in [0, 2^16); the top one keeps the sign (floor carries).
-  __device__ void normalize() {
-#pragma unroll
-    for (int j = 0; j + 1 < kDotDigits; ++j) {
-      const int64_t c = d[j] >> 16;
-      d[j] -= c * (int64_t(1) << 16);
-      d[j + 1] += c;
-    }
-  }
+  // The 128-bit integer rounded by the fp16 sum's rounding (units of 2^-24),
+  // then scaled by 2^-24, which is exact for these magnitudes.
   __device__ double value() const {
-    if ((nf & 4u) || (nf & 3u) == 3u) return __builtin_nan("");
-    if (nf & 1u) return __builtin_inf();
-    if (nf & 2u) return -__builtin_inf();
     F16DotExact t = *this;
-    t.normalize();
-    // The 128-bit two's-complement integer d0 + d1 2^16 + d2 2^32 + d3 2^48
-    // (units of 2^-48), rounded by the fp16 sum's rounding (units of 2^-24)
-    // and scaled by 2^-24, which is exact for these magnitudes.
-    const uint64_t low = (uint64_t)t.d[0] | ((uint64_t)t.d[1] << 16) | ((uint64_t)t.d[2] << 32);
+    t.flush();
+    if (t.nf != 0.0f || t.nf != t.nf) return (double)t.nf;
     ExactAcc e = ExactAcc::zero();
-    e.lo = low | ((uint64_t)t.d[3] << 48);
-    e.hi = (uint64_t)(t.d[3] >> 16);
+    e.lo = t.lo;
+    e.hi = t.hi;
     return __builtin_ldexp(e.value(), -24);
   }
 };
 
-struct DotTerm {
-  int64_t c;    // signed digit increment
-  int dig;      // digit, -1 for zero and non-finite products
-  uint32_t nf;  // flags of a non-finite product
-};
-
-__device__ __forceinline__ DotTerm f16_dot_term(uint32_t a, uint32_t b) {
-  const uint32_t Ea = (a >> 10) & 31u, Eb = (b >> 10) & 31u, Fa = a & 1023u, Fb = b & 1023u;
-  DotTerm t{0, -1, 0u};
-  if (Ea == 31u || Eb == 31u) {
-    const bool zero_a = (a & 0x7FFFu) == 0, zero_b = (b & 0x7FFFu) == 0;
-    const bool nan = (Ea == 31u && Fa) || (Eb == 31u && Fb) || zero_a || zero_b;
-    t.nf = nan ? 4u : (((a ^ b) >> 15) & 1u) ? 2u : 1u;
-    return t;
-  }
-  const uint32_t ma = Ea ? (Fa | 1024u) : Fa, mb = Eb ? (Fb | 1024u) : Fb;
-  const uint32_t M = ma * mb;  // < 2^22
-  if (M == 0) return t;
-  const uint32_t Q = (Ea ? Ea - 1 : 0) + (Eb ? Eb - 1 : 0);
-  const int64_t c = (int64_t)M << (Q & 15u);
-  t.c = ((a ^ b) >> 15) & 1u ? -c : c;
-  t.dig = (int)(Q >> 4);
-  return t;
+__device__ __forceinline__ float f16_bits_to_f32(uint32_t u) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)u);
 }
 
 // Pass 1: every block folds its grid-stride share.  kVec: x and z share their
@@ -294,34 +286,10 @@ __global__ __launch_bounds__(1024) void exact_f16_dot_kernel(const uint16_t* __r
                                                              const uint16_t* __restrict__ z, Range r,
                                                              F16DotExact* partials) {
   __shared__ F16DotExact lds[kMaxWaves];
-  constexpr int V = kVec ? 8 : 1;
   const int64_t B = blockDim.x, tid = threadIdx.x;
-  int64_t acc[kDotDigits] = {0, 0, 0, 0};
-  uint32_t nf = 0;
-  auto fold = [&](const DotTerm (&tm)[V]) {
-    uint32_t mine = 0;
-#pragma unroll
-    for (int i = 0; i < V; ++i) {
-      if (tm[i].dig >= 0) mine |= 1u << tm[i].dig;
-      nf |= tm[i].nf;
-    }
-#pragma unroll
-    for (int j = 0; j < kDotDigits; ++j) {
-      if (__builtin_amdgcn_ballot_w64((mine >> j) & 1u) != 0) {
-#pragma unroll
-        for (int i = 0; i < V; ++i) acc[j] += tm[i].dig == j ? tm[i].c : 0;
-      }
-    }
-  };
-  auto carry = [&]() {  // keeps every digit far below 2^63 whatever the grid
-#pragma unroll
-    for (int j = 0; j + 1 < kDotDigits; ++j) {
-      const int64_t c = acc[j] >> 16;
-      acc[j] -= c * (int64_t(1) << 16);
-      acc[j + 1] += c;
-    }
-  };
+  F16DotExact acc = F16DotExact::zero();
   if constexpr (kVec) {
+    constexpr int V = 8;
     const uint16_t* xv = x + r.head;
     const uint16_t* zv = z + r.head;
     const int64_t nchunk = (r.nvec + B * U - 1) / (B * U);
@@ -336,41 +304,28 @@ __global__ __launch_bounds__(1024) void exact_f16_dot_kernel(const uint16_t* __r
         b[u] = in ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(zv + vi * V)) : u32x4{0u, 0u, 0u, 0u};
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        DotTerm tm[V];
+      for (int u = 0; u < U; ++u)
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          tm[2 * k] = f16_dot_term(a[u][k] & 0xFFFFu, b[u][k] & 0xFFFFu);
-          tm[2 * k + 1] = f16_dot_term(a[u][k] >> 16, b[u][k] >> 16);
+          acc.add(f16_bits_to_f32(a[u][k]) * f16_bits_to_f32(b[u][k]));          // exact in fp32
+          acc.add(f16_bits_to_f32(a[u][k] >> 16) * f16_bits_to_f32(b[u][k] >> 16));
         }
-        fold(tm);
-      }
-      carry();
+      acc.flush();  // chains of at most 8 U terms
     }
     if (blockIdx.x == gridDim.x - 1) {  // unaligned head and the tail, one element per lane
-      DotTerm tm[V];
-#pragma unroll
-      for (int i = 0; i < V; ++i) tm[i] = DotTerm{0, -1, 0u};
-      if (tid < r.head) tm[0] = f16_dot_term(x[tid], z[tid]);
-      if (tid < r.tail) tm[1] = f16_dot_term(x[r.tail_start + tid], z[r.tail_start + tid]);
-      fold(tm);
+      if (tid < r.head) acc.add(f16_bits_to_f32(x[tid]) * f16_bits_to_f32(z[tid]));
+      if (tid < r.tail) acc.add(f16_bits_to_f32(x[r.tail_start + tid]) * f16_bits_to_f32(z[r.tail_start + tid]));
     }
   } else {
     for (int64_t c = blockIdx.x; c * B < r.n; c += gridDim.x) {
       const int64_t i = c * B + tid;
-      DotTerm tm[1] = {DotTerm{0, -1, 0u}};
-      if (i < r.n) tm[0] = f16_dot_term(x[i], z[i]);
-      fold(tm);
-      carry();
+      if (i < r.n) acc.add(f16_bits_to_f32(x[i]) * f16_bits_to_f32(z[i]));
+      acc.flush();
     }
   }
-  F16DotExact s = F16DotExact::zero();
-#pragma unroll
-  for (int j = 0; j < kDotDigits; ++j) s.d[j] = acc[j];
-  s.nf = nf;
-  s.normalize();
-  s = block_reduce(s, MergeOp<F16DotExact>{}, lds);
-  if (tid == 0) partials[blockIdx.x] = s;
+  acc.flush();
+  acc = block_reduce(acc, MergeOp<F16DotExact>{}, lds);
+  if (tid == 0) partials[blockIdx.x] = acc;
 }
 
 static __global__ __launch_bounds__(256) void exact_f16_dot_final_kernel(const F16DotExact* partials, int g,
