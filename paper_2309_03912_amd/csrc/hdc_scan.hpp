@@ -47,6 +47,63 @@ __device__ __forceinline__ T shfl_up_words(T v, int d) {
   return r;
 }
 
+// Move every 32-bit word of `v` through one DPP control; lanes outside
+// kRowMask, or without a source lane, keep their own value.
+template <int kCtrl, int kRowMask, class T>
+__device__ __forceinline__ T dpp_words(T v) {
+  constexpr int W = sizeof(T) / 4;
+  int w[W];
+  __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+  for (int i = 0; i < W; ++i) w[i] = __builtin_amdgcn_update_dpp(w[i], w[i], kCtrl, kRowMask, 0xF, false);
+  T r;
+  __builtin_memcpy(&r, w, sizeof(T));
+  return r;
+}
+
+// Inclusive scan over the lanes of a wavefront in lane order (merge(lower,
+// higher)), with DPP moves only: row_shr 1, 2, 4, 8 inside rows of 16
+// lanes, then row_bcast:15 (rows 1 and 3 take the end of the row before) and
+// row_bcast:31 (rows 2 and 3 take lane 31).  kRows16: only row 0 matters.
+template <class Acc, bool kRows16 = false>
+__device__ __forceinline__ Acc wave_incl_scan(Acc v) {
+  const int lane = threadIdx.x & 63, r = lane & 15;
+  {
+    const Acc u = dpp_words<0x111, 0xF>(v);
+    if (r >= 1) v = Acc::merge(u, v);
+  }
+  {
+    const Acc u = dpp_words<0x112, 0xF>(v);
+    if (r >= 2) v = Acc::merge(u, v);
+  }
+  {
+    const Acc u = dpp_words<0x114, 0xF>(v);
+    if (r >= 4) v = Acc::merge(u, v);
+  }
+  {
+    const Acc u = dpp_words<0x118, 0xF>(v);
+    if (r >= 8) v = Acc::merge(u, v);
+  }
+  if constexpr (!kRows16) {
+    {
+      const Acc u = dpp_words<0x142, 0xA>(v);
+      if (lane & 16) v = Acc::merge(u, v);
+    }
+    {
+      const Acc u = dpp_words<0x143, 0xC>(v);
+      if (lane >= 32) v = Acc::merge(u, v);
+    }
+  }
+  return v;
+}
+
+// The value of the lane below (wave_shr:1); lane 0 gets `first`.
+template <class Acc>
+__device__ __forceinline__ Acc wave_shift_up1(Acc v, const Acc& first) {
+  const Acc u = dpp_words<0x138, 0xF>(v);
+  return (threadIdx.x & 63) == 0 ? first : u;
+}
+
 // Exclusive scan of fold states over a block (thread order).  Returns the
 // thread's exclusive prefix; *total receives the block total (all threads).
 // `lds` holds kMaxWaves states.
@@ -126,8 +183,6 @@ struct SegSpec {
   int64_t m;
 };
 
-constexpr int64_t kNoBoundary = INT64_MAX;
-
 // First index i in [0, m) with off[i] >= p (m if none), by one wavefront:
 // every round probes 64 evenly spaced offsets, so 100,000 segments take three
 // rounds.  The result is wavefront-uniform.
@@ -150,18 +205,10 @@ __device__ __forceinline__ int64_t wave_lower_bound(const int64_t* __restrict__ 
   return ge == 0 ? hi : lo + __builtin_ctzll(ge);
 }
 
-__device__ __forceinline__ int64_t read_lane_i64(int64_t v, int lane) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), lane);
-  return (int64_t)((uint64_t)lo | ((uint64_t)hi << 32));
-}
-
 // One wavefront's part of a tile: loading, terms, the fold states of the
 // fixed order above, and the outputs.  For a segmented scan (Acc a SegAcc)
-// the wavefront also marks the segment starts inside its part: it finds the
-// first boundary at or after its start with a 64-way search of the offsets,
-// holds the next 64 boundaries in its lanes, and sets bit e of head[q] in the
-// lane that owns each boundary position.  Outputs are written only inside
+// each lane takes the segment-start bits of its elements from the tile's
+// bitmap (tile_heads) into `hmask`; outputs are written only inside
 // [off[0], off[S]).
 template <class F, class S, class Acc>
 struct ScanWave {
@@ -178,7 +225,7 @@ struct ScanWave {
   Acc ex[Q];                       // exclusive prefix of this lane within chunk q
   Acc wc[Q];                       // fold of chunks 0..q-1 of this wavefront
   Acc wave_total;
-  uint32_t head[Q];                // segmented: bit e set if element (q, e) starts a segment
+  uint32_t hmask;                  // segmented: bit q V + e set if element (q, e) starts a segment
   int64_t out_lo, out_hi;          // segmented: outputs are written in [out_lo, out_hi)
 
   __device__ int64_t index(int q, int e) const { return wbase + (int64_t)q * 64 * V + (int64_t)lane * V + e; }
@@ -202,36 +249,53 @@ struct ScanWave {
           v[q * V + e] = i < n ? x[i] : elem_t<S>{};
         }
     }
-    if constexpr (kSeg) mark_heads(seg);  // overlaps the loads in flight
+    if constexpr (kSeg) {
+      out_lo = seg.off[0];
+      out_hi = seg.off[seg.m - 1];
+    }
   }
 
-  __device__ void mark_heads(const SegSpec& seg) {
-    out_lo = seg.off[0];
-    out_hi = seg.off[seg.m - 1];
-    int64_t base = wave_lower_bound(seg.off, seg.m, wbase, lane);
-    int at = 0;
-    int64_t mine = base + lane < seg.m ? seg.off[base + lane] : kNoBoundary;
+  // What emit() reads of this lane's elements (the terms; for int32 the
+  // inputs), parked in LDS while the block waits for its carry, so that the
+  // wait's registers do not add to the tile's.  Word k of thread i is at
+  // park[k * blockDim + i].
+  __device__ void park(uint32_t* park_lds) const {
+#pragma unroll
+    for (int k = 0; k < kScanE; ++k) {
+      uint32_t w;
+      if constexpr (std::is_same_v<S, I32>)
+        w = (uint32_t)v[k];
+      else
+        w = __builtin_bit_cast(uint32_t, t[k]);
+      park_lds[k * blockDim.x + threadIdx.x] = w;
+    }
+  }
+  __device__ void unpark(const uint32_t* park_lds) {
+#pragma unroll
+    for (int k = 0; k < kScanE; ++k) {
+      const uint32_t w = park_lds[k * blockDim.x + threadIdx.x];
+      if constexpr (std::is_same_v<S, I32>)
+        v[k] = (int32_t)w;
+      else
+        t[k] = __builtin_bit_cast(float, w);
+    }
+  }
+
+  // This lane's segment-start bits from the tile bitmap (bit p: tile
+  // position p starts a segment).  A lane's V elements of a chunk are V
+  // consecutive bits inside one 32-bit word.
+  __device__ void take_heads(const uint32_t* bits, int64_t tile_start) {
+    hmask = 0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      head[q] = 0;
-      const int64_t c0 = wbase + (int64_t)q * 64 * V, c1 = c0 + 64 * V;
-      for (;;) {  // wavefront-uniform: the boundaries in [c0, c1), in order
-        const int64_t b = read_lane_i64(mine, at);
-        if (b >= c1) break;
-        const int64_t d = b - c0;  // >= 0: earlier boundaries were consumed before
-        if (lane == (int)(d / V)) head[q] |= 1u << (int)(d % V);
-        if (++at == 64) {
-          base += 64;
-          at = 0;
-          mine = base + lane < seg.m ? seg.off[base + lane] : kNoBoundary;
-        }
-      }
+      const int64_t p = index(q, 0) - tile_start;
+      hmask |= ((bits[p >> 5] >> (p & 31)) & ((1u << V) - 1u)) << (q * V);
     }
   }
 
   __device__ bool is_head(int q, int e) const {
     if constexpr (kSeg)
-      return (head[q] >> e) & 1u;
+      return (hmask >> (q * V + e)) & 1u;
     else
       return false;
   }
@@ -273,15 +337,8 @@ struct ScanWave {
     Acc run = Acc::zero();
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      Acc incl = tot[q];
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const Acc u = shfl_up_words(incl, d);
-        if (lane >= d) incl = Acc::merge(u, incl);
-      }
-      Acc e = shfl_up_words(incl, 1);
-      if (lane == 0) e = Acc::zero();
-      ex[q] = e;
+      const Acc incl = wave_incl_scan(tot[q]);
+      ex[q] = wave_shift_up1(incl, Acc::zero());
       wc[q] = run;
       run = Acc::merge(run, read_lane(incl, 63));
     }
@@ -334,21 +391,21 @@ struct ScanWave {
 };
 
 // Exclusive fold of the wavefront totals of a block in wave order; *total
-// receives the block total.  `lds` holds kMaxWaves states.
+// receives the block total.  Every wavefront loads the (at most 16) totals
+// into its first lanes and scans them with fixed DPP moves, so the
+// results are wavefront-uniform (scalar registers) and the fold costs the
+// tile no vector registers beyond the moves.  `lds` holds kMaxWaves
+// states.
 template <class Acc>
 __device__ __forceinline__ Acc block_wave_prefix(const Acc& wave_total, Acc* lds, Acc* total) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   if (lane == 0) lds[wid] = wave_total;
   __syncthreads();
-  Acc before = Acc::zero(), all = Acc::zero();
-  for (int i = 0; i < nw; ++i) {
-    const Acc w = lds[i];
-    if (i < wid) before = Acc::merge(before, w);
-    all = Acc::merge(all, w);
-  }
+  const Acc v = wave_incl_scan<Acc, true>(lane < nw ? lds[lane] : Acc::zero());  // nw <= 16: row 0
+  *total = read_lane(v, nw - 1);
+  const Acc prev = read_lane(v, wid > 0 ? wid - 1 : 0);
   __syncthreads();
-  *total = all;
-  return before;
+  return wid > 0 ? prev : Acc::zero();
 }
 
 template <class F, class S, class Acc>
@@ -360,14 +417,45 @@ __device__ __forceinline__ ScanWave<F, S, Acc> scan_wave_at(int64_t tile, int64_
   return w;
 }
 
+// Segment starts of the tile [t0, t0 + len) as a bitmap in LDS (len / 32
+// words; bit p: position t0 + p starts a segment), built by the whole block:
+// wavefront 0 finds the first boundary at or after t0 with a 64-way search,
+// then every thread takes one boundary per round until they pass the tile.
+// Then each wavefront takes its lanes' bits (ScanWave::take_heads).  Empty
+// segments repeat a boundary, which sets the same bit again.
+constexpr int kTileWords = 1024 * kScanE / 32;  // bitmap words of the largest tile
+
+template <class W>
+__device__ void tile_heads(W& w, const SegSpec& seg, int64_t t0, int64_t len, uint32_t* bits, int64_t* first) {
+  const int tid = threadIdx.x;
+  for (int64_t i = tid; i < len / 32; i += blockDim.x) bits[i] = 0;
+  if (tid < 64) {
+    const int64_t b = wave_lower_bound(seg.off, seg.m, t0, tid);
+    if (tid == 0) *first = b;
+  }
+  __syncthreads();
+  const int64_t t1 = t0 + len;
+  for (int64_t j = *first + tid; j < seg.m; j += blockDim.x) {
+    const int64_t b = seg.off[j];  // >= t0: j is at or after the first such boundary
+    if (b >= t1) break;            // the offsets do not decrease: later ones are past the tile too
+    atomicOr(&bits[(b - t0) >> 5], 1u << ((b - t0) & 31));
+  }
+  __syncthreads();
+  w.take_heads(bits, t0);
+}
+
 // Pass A: the sum of every tile.
 template <class F, class S, class Acc, bool kAligned>
   requires device_callable<F>
 __global__ __launch_bounds__(1024) void scan_tile_sums_kernel(F f, const elem_t<S>* x, int64_t n, SegSpec seg,
                                                               Acc* sums) {
   __shared__ Acc lds[kMaxWaves];
+  __shared__ uint32_t heads_sh[IsSeg<Acc>::value ? kTileWords : 1];
+  __shared__ int64_t first_sh;
   auto w = scan_wave_at<F, S, Acc>(blockIdx.x, n);
   w.template load<kAligned>(x, seg);
+  if constexpr (IsSeg<Acc>::value)
+    tile_heads(w, seg, (int64_t)blockIdx.x * blockDim.x * kScanE, (int64_t)blockDim.x * kScanE, heads_sh, &first_sh);
   w.fold(f);
   Acc total;
   (void)block_wave_prefix(w.wave_total, lds, &total);
@@ -420,8 +508,12 @@ __global__ __launch_bounds__(1024) void scan_tiles_kernel(F f, const elem_t<S>* 
                                                           const Acc* offsets, typename ScanOut<Acc>::T* y,
                                                           int exclusive) {
   __shared__ Acc lds[kMaxWaves];
+  __shared__ uint32_t heads_sh[IsSeg<Acc>::value ? kTileWords : 1];
+  __shared__ int64_t first_sh;
   auto w = scan_wave_at<F, S, Acc>(blockIdx.x, n);
   w.template load<kAligned>(x, seg);
+  if constexpr (IsSeg<Acc>::value)
+    tile_heads(w, seg, (int64_t)blockIdx.x * blockDim.x * kScanE, (int64_t)blockDim.x * kScanE, heads_sh, &first_sh);
   w.fold(f);
   Acc total;
   const Acc before = block_wave_prefix(w.wave_total, lds, &total);
@@ -429,7 +521,7 @@ __global__ __launch_bounds__(1024) void scan_tiles_kernel(F f, const elem_t<S>* 
 }
 
 // ---------------------------------------------------------------------------
-// Single pass with decoupled look-back
+// Single pass with a tree of tile totals
 // ---------------------------------------------------------------------------
 
 // The carry between tiles: fp64 for the float folds (so a chain of up to
@@ -582,26 +674,20 @@ __host__ __device__ constexpr int64_t tree_nodes(int64_t tiles) {
 // order, returned in every lane.  Lane l's value is in words
 // slot[i * 64 + l], i < kWords (LDS).
 template <class C>
+struct CarryFold {  // a carry with the merge interface of the scans
+  typename C::T t;
+  __device__ static CarryFold merge(const CarryFold& a, const CarryFold& b) { return {C::add(a.t, b.t)}; }
+};
+
+template <class C>
 __device__ __forceinline__ typename C::T wave_ordered_fold(const uint32_t* slot, int m) {
   constexpr int W = C::kWords;
   const int lane = threadIdx.x & 63;
   uint32_t w[W];
 #pragma unroll
   for (int k = 0; k < W; ++k) w[k] = slot[k * 64 + lane];
-  typename C::T x = C::unpack(w);
-  for (int d = 1; d < m; d <<= 1) {
-    uint32_t u[W];
-    C::pack(x, w);
-#pragma unroll
-    for (int k = 0; k < W; ++k) u[k] = (uint32_t)__shfl_up((int)w[k], d, 64);
-    const typename C::T lower = C::unpack(u);
-    if (lane >= d) x = C::add(lower, x);
-  }
-  uint32_t r[W];
-  C::pack(x, w);
-#pragma unroll
-  for (int k = 0; k < W; ++k) r[k] = (uint32_t)__builtin_amdgcn_readlane((int)w[k], m - 1);
-  return C::unpack(r);
+  const CarryFold<C> x = wave_incl_scan(CarryFold<C>{C::unpack(w)});  // lanes >= m never reach lane m - 1
+  return read_lane(x, m - 1).t;
 }
 
 // Run by one whole wavefront; lane 0 publishes.  `tiles` is the grid size;
@@ -685,19 +771,26 @@ __global__ __launch_bounds__(1024) void scan_onepass_kernel(F f, const elem_t<S>
   __shared__ int64_t tile_sh;
   __shared__ typename C::T carry_sh;
   __shared__ uint32_t slots[kTreeLevels * C::kWords * 64];
+  __shared__ uint32_t heads_sh[IsSeg<Acc>::value ? kTileWords : 1];
+  __shared__ int64_t first_sh;
+  __shared__ uint32_t park_sh[IsSeg<Acc>::value ? 1024 * kScanE : 1];
   if (threadIdx.x == 0) tile_sh = (int64_t)atomicAdd(lb.ticket, 1u);
   __syncthreads();
   const int64_t tile = tile_sh;
   auto w = scan_wave_at<F, S, Acc>(tile, n);
   w.template load<kAligned>(x, seg);
+  if constexpr (IsSeg<Acc>::value)
+    tile_heads(w, seg, tile * blockDim.x * kScanE, (int64_t)blockDim.x * kScanE, heads_sh, &first_sh);
   w.fold(f);
   Acc total;
   const Acc before = block_wave_prefix(w.wave_total, lds, &total);
+  if constexpr (IsSeg<Acc>::value) w.park(park_sh);  // each thread reads back only its own words
   if (threadIdx.x < 64) {
     const typename C::T carry = scan_tree_carry<C>(lb, tile, (int64_t)gridDim.x, C::of(total), slots);
     if (threadIdx.x == 0) carry_sh = carry;
   }
   __syncthreads();
+  if constexpr (IsSeg<Acc>::value) w.unpark(park_sh);
   w.template emit<kOutAligned>(f, Acc::merge(C::to(carry_sh), before), exclusive, y);
 }
 
