@@ -724,14 +724,36 @@ __device__ typename C::T scan_tree_carry(const ScanLB& lb, int64_t t, int64_t ti
   int pub = 0;
   bool all = false;
   for (uint32_t polls = 0;; ++polls) {
-    for (int k = 0; k < K; ++k) {
-      if ((pend >> k) & 1u) {
-        uint32_t v[W];
-        const int64_t j = ((t >> (6 * (k + 1))) << 6) + lane;
-        if (lb_read<W>(lb.node + start(k) + (int64_t)W * j, v)) {
+    // Levels in groups of kBatch: the reads of a group are all issued before
+    // any of them is examined, so a poll of K <= kBatch levels costs one round
+    // trip (two-word carries; three-word carries take one level at a time to
+    // spare registers).
+    constexpr int kBatch = W == 2 ? 3 : 1;
+    for (int k0 = 0; k0 < K; k0 += kBatch) {
+      uint64_t got[kBatch][W];
 #pragma unroll
-          for (int i = 0; i < W; ++i) slots[(k * W + i) * 64 + lane] = v[i];
-          pend &= ~(1u << k);
+      for (int b = 0; b < kBatch; ++b) {
+        const int k = k0 + b;
+        if (k < K && ((pend >> k) & 1u)) {
+          const int64_t j = ((t >> (6 * (k + 1))) << 6) + lane;
+#pragma unroll
+          for (int i = 0; i < W; ++i)
+            got[b][i] = __hip_atomic_load(lb.node + start(k) + (int64_t)W * j + i, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        const int k = k0 + b;
+        if (k < K && ((pend >> k) & 1u)) {
+          bool ok = true;
+#pragma unroll
+          for (int i = 0; i < W; ++i) ok = ok && (got[b][i] >> 32) != 0;
+          if (ok) {
+#pragma unroll
+            for (int i = 0; i < W; ++i) slots[(k * W + i) * 64 + lane] = (uint32_t)got[b][i];
+            pend &= ~(1u << k);
+          }
         }
       }
     }
