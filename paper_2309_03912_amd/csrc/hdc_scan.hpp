@@ -255,32 +255,6 @@ struct ScanWave {
     }
   }
 
-  // What emit() reads of this lane's elements (the terms; for int32 the
-  // inputs), parked in LDS while the block waits for its carry, so that the
-  // wait's registers do not add to the tile's.  Word k of thread i is at
-  // park[k * blockDim + i].
-  __device__ void park(uint32_t* park_lds) const {
-#pragma unroll
-    for (int k = 0; k < kScanE; ++k) {
-      uint32_t w;
-      if constexpr (std::is_same_v<S, I32>)
-        w = (uint32_t)v[k];
-      else
-        w = __builtin_bit_cast(uint32_t, t[k]);
-      park_lds[k * blockDim.x + threadIdx.x] = w;
-    }
-  }
-  __device__ void unpark(const uint32_t* park_lds) {
-#pragma unroll
-    for (int k = 0; k < kScanE; ++k) {
-      const uint32_t w = park_lds[k * blockDim.x + threadIdx.x];
-      if constexpr (std::is_same_v<S, I32>)
-        v[k] = (int32_t)w;
-      else
-        t[k] = __builtin_bit_cast(float, w);
-    }
-  }
-
   // This lane's segment-start bits from the tile bitmap (bit p: tile
   // position p starts a segment).  A lane's V elements of a chunk are V
   // consecutive bits inside one 32-bit word.
@@ -795,7 +769,6 @@ __global__ __launch_bounds__(1024) void scan_onepass_kernel(F f, const elem_t<S>
   __shared__ uint32_t slots[kTreeLevels * C::kWords * 64];
   __shared__ uint32_t heads_sh[IsSeg<Acc>::value ? kTileWords : 1];
   __shared__ int64_t first_sh;
-  __shared__ uint32_t park_sh[IsSeg<Acc>::value ? 1024 * kScanE : 1];
   if (threadIdx.x == 0) tile_sh = (int64_t)atomicAdd(lb.ticket, 1u);
   __syncthreads();
   const int64_t tile = tile_sh;
@@ -806,13 +779,11 @@ __global__ __launch_bounds__(1024) void scan_onepass_kernel(F f, const elem_t<S>
   w.fold(f);
   Acc total;
   const Acc before = block_wave_prefix(w.wave_total, lds, &total);
-  if constexpr (IsSeg<Acc>::value) w.park(park_sh);  // each thread reads back only its own words
   if (threadIdx.x < 64) {
     const typename C::T carry = scan_tree_carry<C>(lb, tile, (int64_t)gridDim.x, C::of(total), slots);
     if (threadIdx.x == 0) carry_sh = carry;
   }
   __syncthreads();
-  if constexpr (IsSeg<Acc>::value) w.unpark(park_sh);
   w.template emit<kOutAligned>(f, Acc::merge(C::to(carry_sh), before), exclusive, y);
 }
 
