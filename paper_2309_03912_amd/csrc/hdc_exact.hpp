@@ -101,54 +101,52 @@ struct Bf16Exact {
   }
 };
 
-// Add the bf16 value with bits u to the lane's digits `acc` (digit `dig` of
-// the batch already known) -- the decode.
-struct Bf16Term {
-  int64_t c;    // signed digit increment
-  int dig;      // digit index, -1 for zeros and non-finite values
-  uint32_t nf;  // flags of a non-finite value
-};
-
-__device__ __forceinline__ Bf16Term bf16_term(uint16_t u) {
-  const uint32_t E = (u >> 7) & 0xFFu, M = u & 0x7Fu;
-  Bf16Term t{0, -1, 0u};
-  if (E == 0xFFu) {
-    t.nf = M ? 4u : ((u >> 15) ? 2u : 1u);
-    return t;
-  }
-  const uint32_t m = E ? (M | 0x80u) : M;
-  if (m == 0) return t;
-  const uint32_t q = E ? E - 1 : 0;
-  const int64_t c = (int64_t)m << (q & 31);
-  t.c = (u >> 15) ? -c : c;
-  t.dig = (int)(q >> 5);
-  return t;
-}
-
 // Pass 1: every block folds its grid-stride share of 16-byte vectors (8
-// values; head and tail elements by the last block) into one state.
+// values; head and tail elements by the last block) into one state.  The
+// decode is branch-free: a value's term m 2^(q mod 32) (an integer below
+// 2^39, signed) is formed as an fp64 number, which holds it exactly, and
+// added to the fp64 accumulator of digit q / 32 -- exact while a lane takes
+// fewer than 2^14 terms, which the launch guarantees (at most 1024 vectors
+// per lane, kExactVecsPerLane).  A wavefront adds to a digit's accumulator only
+// when one of its lanes has a term for that digit (a ballot).  Infinities and
+// NaNs contribute no term; their flags are taken on a separate, rare path.
+constexpr int64_t kExactVecsPerLane = 1024;  // 8192 terms (+2 head/tail) < 2^14
+
 template <int U>
 __global__ __launch_bounds__(1024) void exact_bf16_kernel(const uint16_t* __restrict__ x, Range r,
                                                           Bf16Exact* partials) {
   __shared__ Bf16Exact lds[kMaxWaves];
   constexpr int V = 8;
   const int64_t B = blockDim.x, tid = threadIdx.x;
-  int64_t acc[kExactFoldDigits];
+  double acc[kExactFoldDigits];
 #pragma unroll
-  for (int j = 0; j < kExactFoldDigits; ++j) acc[j] = 0;
+  for (int j = 0; j < kExactFoldDigits; ++j) acc[j] = 0.0;
   uint32_t nf = 0;
-  auto fold = [&](const Bf16Term (&tm)[V]) {  // one vector's eight values
-    uint32_t mine = 0;  // digits this lane's values touch
+  auto fold = [&](const uint32_t (&u)[V]) {  // u: bf16 bits, 0 for no value
+    double t[V];
+    int d[V];
+    uint32_t mine = 0;
+    bool special = false;
 #pragma unroll
     for (int i = 0; i < V; ++i) {
-      if (tm[i].dig >= 0) mine |= 1u << tm[i].dig;
-      nf |= tm[i].nf;
+      const uint32_t E = (u[i] >> 7) & 0xFFu, M = u[i] & 0x7Fu;
+      special = special || E == 0xFFu;
+      const int32_t m = E == 0xFFu ? 0 : (int32_t)(E ? (M | 0x80u) : M);
+      const uint32_t q = E ? E - 1 : 0;
+      t[i] = __builtin_ldexp((double)((u[i] >> 15) ? -m : m), (int)(q & 31u));  // exact
+      d[i] = (int)(q >> 5);
+      mine |= m ? 1u << d[i] : 0u;
+    }
+    if (__builtin_amdgcn_ballot_w64(special) != 0) {  // rare: infinities and NaNs present
+#pragma unroll
+      for (int i = 0; i < V; ++i)
+        if (((u[i] >> 7) & 0xFFu) == 0xFFu) nf |= (u[i] & 0x7Fu) ? 4u : ((u[i] >> 15) ? 2u : 1u);
     }
 #pragma unroll
     for (int j = 0; j < kExactFoldDigits; ++j) {
-      if (__builtin_amdgcn_ballot_w64((mine >> j) & 1u) != 0) {  // uniform: some lane touches digit j
+      if (__builtin_amdgcn_ballot_w64((mine >> j) & 1u) != 0) {  // uniform: some lane has a term here
 #pragma unroll
-        for (int i = 0; i < V; ++i) acc[j] += tm[i].dig == j ? tm[i].c : 0;
+        for (int i = 0; i < V; ++i) acc[j] += d[i] == j ? t[i] : 0.0;
       }
     }
   };
@@ -158,42 +156,31 @@ __global__ __launch_bounds__(1024) void exact_bf16_kernel(const uint16_t* __rest
     const int64_t base = c * B * U + tid;
     u32x4 a[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t vi = base + u * B;
-      a[u] = vi < r.nvec ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(xv + vi * V))
+    for (int w = 0; w < U; ++w) {
+      const int64_t vi = base + w * B;
+      a[w] = vi < r.nvec ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(xv + vi * V))
                          : u32x4{0u, 0u, 0u, 0u};
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      Bf16Term tm[V];
+    for (int w = 0; w < U; ++w) {
+      uint32_t u[V];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const uint32_t w = a[u][k];
-        tm[2 * k] = bf16_term((uint16_t)w);
-        tm[2 * k + 1] = bf16_term((uint16_t)(w >> 16));
+        u[2 * k] = a[w][k] & 0xFFFFu;
+        u[2 * k + 1] = a[w][k] >> 16;
       }
-      fold(tm);
-    }
-    // Carry digits 0..6 up once per step, so that they stay far below 2^63
-    // however many steps a lane takes; digit 7 only takes values >= 2^91.
-#pragma unroll
-    for (int j = 0; j + 1 < kExactFoldDigits; ++j) {
-      const int64_t cy = acc[j] >> 32;
-      acc[j] -= cy * (int64_t(1) << 32);
-      acc[j + 1] += cy;
+      fold(u);
     }
   }
   if (blockIdx.x == gridDim.x - 1) {  // unaligned head and the tail, one element per lane
-    Bf16Term tm[V];
-#pragma unroll
-    for (int i = 0; i < V; ++i) tm[i] = Bf16Term{0, -1, 0u};
-    if (tid < r.head) tm[0] = bf16_term(x[tid]);
-    if (tid < r.tail) tm[1] = bf16_term(x[r.tail_start + tid]);
-    fold(tm);
+    uint32_t u[V] = {};
+    if (tid < r.head) u[0] = x[tid];
+    if (tid < r.tail) u[1] = x[r.tail_start + tid];
+    fold(u);
   }
   Bf16Exact s = Bf16Exact::zero();
 #pragma unroll
-  for (int j = 0; j < kExactFoldDigits; ++j) s.d[j] = acc[j];
+  for (int j = 0; j < kExactFoldDigits; ++j) s.d[j] = (int64_t)acc[j];  // integers below 2^53: exact
   s.nf = nf;
   s.normalize();  // digits in [0, 2^32) before the cross-lane sums
   s = block_reduce(s, MergeOp<Bf16Exact>{}, lds);

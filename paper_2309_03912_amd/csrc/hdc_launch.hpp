@@ -86,6 +86,14 @@ inline hdc_status launch_exact_bf16(const void* x, int64_t n, void* out, void* w
   const int u = t.unroll >= 4 ? 4 : t.unroll;
   int64_t g = grid_for(r.nvec, (int64_t)t.block * u, cus, t);
   if (g > 4096) g = 4096;
+  // Enough lanes that none takes more than kExactVecsPerLane vectors (its
+  // fp64 accumulators stay exact), within the partials the workspace holds.
+  const int64_t lanes_needed = (r.nvec + kExactVecsPerLane - 1) / kExactVecsPerLane;
+  const int64_t g_min = (lanes_needed + t.block - 1) / t.block;
+  constexpr int64_t kMaxExactGrid = (int64_t)(kMaxGrid * kPartialBytes / sizeof(Bf16Exact));
+  if (g_min > kMaxExactGrid)
+    return fail(HDC_ERR_UNSUPPORTED, "n = %lld is too large for an exact bf16 sum at block %d", (long long)n, t.block);
+  if (g < g_min) g = g_min;
   Bf16Exact* partials = static_cast<Bf16Exact*>(ws);
   const uint16_t* xp = static_cast<const uint16_t*>(x);
   const dim3 grid((unsigned)g), block(t.block);
