@@ -85,7 +85,9 @@ typedef enum hdc_accum {
                               bit-reproducible.  IDENTITY folds of fp16 or
                               bf16 storage (transform_reduce; map_reduce for
                               fp16) and PRODUCT folds (dot products) of fp16
-                              storage with n < 2^31.  A non-finite term
+                              storage with n < 2^31; bf16 sums take any n
+                              below 2^33 (a larger n may return
+                              HDC_ERR_UNSUPPORTED).  A non-finite term
                               makes the result its IEEE sum of the
                               non-finite terms (inf * 0 is NaN). */
 } hdc_accum;
