@@ -758,9 +758,19 @@ __device__ typename C::T scan_tree_carry(const ScanLB& lb, int64_t t, int64_t ti
 }
 
 // One tile per block; the tile index comes from the ticket, not blockIdx.
+// Waves per SIMD the single-pass kernel is compiled for (1: the compiler's
+// choice).  The plain segmented scan needs a few VGPRs over 64; holding it to
+// 64 (two 1024-thread blocks per CU) spills 32 bytes per lane and still runs
+// 18% faster.  The int64 scans would spill ~100 bytes per lane and slow down.
+template <class Acc>
+struct OnepassWaves : std::integral_constant<int, 1> {};
+template <>
+struct OnepassWaves<SegAcc<PlainAcc>> : std::integral_constant<int, 8> {};
+
 template <class F, class S, class Acc, bool kAligned, bool kOutAligned>
   requires device_callable<F>
-__global__ __launch_bounds__(1024) void scan_onepass_kernel(F f, const elem_t<S>* x, int64_t n, SegSpec seg,
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(OnepassWaves<Acc>::value))) void
+scan_onepass_kernel(F f, const elem_t<S>* x, int64_t n, SegSpec seg,
                                                             ScanLB lb, typename ScanOut<Acc>::T* y, int exclusive) {
   using C = ScanCarry<Acc>;
   __shared__ Acc lds[kMaxWaves];
