@@ -168,7 +168,7 @@ class Case:
 def candidates(op, quick=False):
     blocks = [256, 512, 1024] if quick else [128, 256, 512, 1024]
     unrolls = [2, 4, 8] if quick else [1, 2, 4, 8]
-    gms = [4, 8, 16] if quick else [2, 4, 8, 16, 32]
+    gms = [4, 8, 16] if quick else [2, 4, 8, 16, 32, 64]
     base = [dict(block=b, unroll=u, grid_mult=g) for b, u, g in itertools.product(blocks, unrolls, gms)]
     if op == OP_BATCH:
         return base, [dict(chunk=c) for c in [8192, 16384, 32768, 65536]]
