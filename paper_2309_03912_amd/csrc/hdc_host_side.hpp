@@ -33,31 +33,27 @@ void host_map_range(const F& f, const elem_t<S>* x, elem_t<S>* y, int64_t lo, in
   for (; i < hi; ++i) y[i] = map_elem<F, S>(f, x[i]);
 }
 
-// Blocked fold of [lo, hi): blocks of kHostBlock elements into four
-// interleaved states, block totals merged in order -- short plain-fp32 chains
-// whatever the range length.
+// The fold of one block [b, e) of at most kHostBlock elements: element i
+// goes to state (i - b) mod 4 (four independent chains), and the states meet
+// as (0 + 1) + (2 + 3).  The result is a fixed function of the block's
+// elements.
 constexpr int64_t kHostBlock = 4096;
 
 template <class F, class S, class Acc>
   requires host_callable<F>
-Acc host_fold_range(const F& f, const elem_t<S>* x, const elem_t<S>* z, int64_t lo, int64_t hi) {
-  Acc total = Acc::zero();
-  for (int64_t b = lo; b < hi; b += kHostBlock) {
-    const int64_t e = hi < b + kHostBlock ? hi : b + kHostBlock;
-    Acc part[4] = {Acc::zero(), Acc::zero(), Acc::zero(), Acc::zero()};
-    int64_t i = b;
-    if constexpr (!std::is_same_v<S, I32> && !F::binary) {
-      for (; i + kHostBatch <= e; i += kHostBatch) {  // the same terms as fold_elem, a batch at a time
-        float t[kHostBatch];
-        for (int k = 0; k < kHostBatch; ++k) t[k] = S::widen(x[i + k]);
-        eval_batch(f, t);
-        for (int k = 0; k < kHostBatch; ++k) part[(i - b + k) & 3].add(t[k]);
-      }
+Acc host_fold_block(const F& f, const elem_t<S>* x, const elem_t<S>* z, int64_t b, int64_t e) {
+  Acc part[4] = {Acc::zero(), Acc::zero(), Acc::zero(), Acc::zero()};
+  int64_t i = b;
+  if constexpr (!std::is_same_v<S, I32> && !F::binary) {
+    for (; i + kHostBatch <= e; i += kHostBatch) {  // the same terms as fold_elem, a batch at a time
+      float t[kHostBatch];
+      for (int k = 0; k < kHostBatch; ++k) t[k] = S::widen(x[i + k]);
+      eval_batch(f, t);
+      for (int k = 0; k < kHostBatch; ++k) part[k & 3].add(t[k]);
     }
-    for (; i < e; ++i) fold_elem<F, S>(part[(i - b) & 3], f, x[i], F::binary ? z[i] : x[i]);
-    total = Acc::merge(total, Acc::merge(Acc::merge(part[0], part[1]), Acc::merge(part[2], part[3])));
   }
-  return total;
+  for (; i < e; ++i) fold_elem<F, S>(part[(i - b) & 3], f, x[i], F::binary ? z[i] : x[i]);
+  return Acc::merge(Acc::merge(part[0], part[1]), Acc::merge(part[2], part[3]));
 }
 
 // Split [0, n) into `parts` contiguous ranges; part p is [lo(p), lo(p+1)).
@@ -93,30 +89,35 @@ void host_map(const F& f, const void* x, void* y, int64_t n, int32_t nthreads) {
   });
 }
 
-// Each thread folds its contiguous range; the thread states are merged in
-// thread order (plain: fp32; compensated: fp64 of s + c; integers: wrapping).
+// The array is cut into blocks of kHostBlock elements from its start; the
+// threads fold disjoint runs of whole blocks, and the block states are then
+// merged in block order by one thread (plain: fp32; compensated: fp64 of
+// s + c; integers: wrapping).  So the result does not depend on the thread
+// count.
 template <class F, class S, class Acc>
   requires host_callable<F>
 void host_reduce(const F& f, const void* x, const void* z, int64_t n, void* out, int32_t nthreads) {
   using T = elem_t<S>;
+  const int64_t nb = (n + kHostBlock - 1) / kHostBlock;
+  std::vector<Acc> blk((size_t)nb);
   const int parts = host_threads(nthreads, n);
-  std::vector<Acc> st(parts);
   host_parallel(parts, [&](int p) {
-    st[p] = host_fold_range<F, S, Acc>(f, (const T*)x, (const T*)z, host_part_lo(n, parts, p),
-                                       host_part_lo(n, parts, p + 1));
+    for (int64_t k = host_part_lo(nb, parts, p); k < host_part_lo(nb, parts, p + 1); ++k) {
+      const int64_t e = n < (k + 1) * kHostBlock ? n : (k + 1) * kHostBlock;
+      blk[(size_t)k] = host_fold_block<F, S, Acc>(f, (const T*)x, (const T*)z, k * kHostBlock, e);
+    }
   });
-  if constexpr (std::is_same_v<Acc, PlainAcc>) {
-    float s = 0.0f;
-    for (const Acc& a : st) s += a.s;
-    *static_cast<float*>(out) = s;
-  } else if constexpr (std::is_same_v<Acc, CompAcc>) {
-    double s = 0.0;
-    for (const Acc& a : st) s += __builtin_isfinite(a.s) ? (double)a.s + (double)a.c : (double)a.s;
-    *static_cast<double*>(out) = s;
+  if constexpr (std::is_same_v<Acc, CompAcc>) {  // the cross-block combine in fp64, as on the device
+    double t = 0.0;
+    for (const Acc& a : blk) t += __builtin_isfinite(a.s) ? (double)a.s + (double)a.c : (double)a.s;
+    *static_cast<double*>(out) = t;
   } else {
-    uint64_t s = 0;
-    for (const Acc& a : st) s += a.s;
-    *static_cast<int64_t*>(out) = (int64_t)s;
+    Acc total = Acc::zero();
+    for (const Acc& a : blk) total = Acc::merge(total, a);
+    if constexpr (std::is_same_v<Acc, PlainAcc>)
+      *static_cast<float*>(out) = total.s;
+    else
+      *static_cast<int64_t*>(out) = (int64_t)total.s;
   }
 }
 

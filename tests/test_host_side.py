@@ -108,3 +108,15 @@ def test_device_only_callable_cannot_run_on_the_host():
     bad = _probe(["-DPROBE_HOST_DEVONLY"])
     assert bad.returncode != 0
     assert "constraints not satisfied" in bad.stderr or "no matching" in bad.stderr
+
+
+@pytest.mark.parametrize("acc", ["plain", "compensated"])
+def test_host_reduce_independent_of_thread_count(acc):
+    """Blocks are cut from the array start and merged in block order: the same bits for any thread count."""
+    x = synth.uniform_pm1_f32(44, 0, (1 << 20) + 4099)
+    fn = {"fn": "horner", "coef": synth.horner_coefficients(8)}
+    ref = hdc.host_transform_reduce(x, fn, acc, threads=1).item()
+    for threads in (2, 3, 7, 16):
+        assert hdc.host_transform_reduce(x, fn, acc, threads=threads).item() == ref, threads
+    r = oracle.reduce(fn, x)
+    assert abs(ref - r["exact"]) <= 1e-6 * r["abs_sum"]
