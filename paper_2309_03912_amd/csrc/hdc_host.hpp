@@ -47,7 +47,7 @@ struct Tuning {
 constexpr int64_t kMaxGrid = 65536;  // upper bound on pass-1 blocks
 constexpr size_t kPartialBytes = 32;  // every fold state fits 32 bytes
 
-inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+constexpr size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 inline size_t reduce_workspace_bytes() { return round_up(kMaxGrid * kPartialBytes, 256); }
 
@@ -183,7 +183,7 @@ hdc_status run_segmented_scan(const hdc_functor& f, hdc_dtype dt, const void* x,
 // elements: the larger of the three-pass need (tile sums and offsets, at most
 // 16 bytes each per tile) and the single-pass need (256-byte header, then at
 // most 3 words of 8 bytes per tile).
-inline size_t scan_workspace_bytes(int64_t n) {
+constexpr size_t scan_workspace_bytes(int64_t n) {
   const int64_t G = n / 1024 + 1;
   return 256 + 2 * round_up((size_t)G * 24, 256);
 }

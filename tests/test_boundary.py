@@ -185,6 +185,17 @@ def test_host_only_callable_cannot_instantiate_a_kernel():
     assert good.returncode == 0, good.stderr
 
 
+def test_scan_tree_shape_and_workspace_bound():
+    """Compile-time checks of the carry tree's levels and node counts, and that its state fits the
+    scan workspace for every tile size (tests/compile_probes/scan_tree.hip)."""
+    src = os.path.join(ROOT, "tests", "compile_probes", "scan_tree.hip")
+    cmd = ["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-std=c++20", "-fsyntax-only",
+           "-fconstexpr-steps=100000000", "-I", os.path.join(ROOT, "include"),
+           "-I", os.path.join(ROOT, "paper_2309_03912_amd", "csrc"), src]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
 def test_segmented_scan_rejects_bad_arguments():
     L = hdc.lib()
     ident = fn({"fn": "identity"})
