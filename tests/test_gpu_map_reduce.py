@@ -486,3 +486,20 @@ def test_exact_fp16_dot_nonfinite():
     x[9000] = 1.0
     x[77] = math.nan
     assert math.isnan(dot())
+
+
+def test_exact_bf16_sum_raises_a_small_grid():
+    """With 64-thread blocks and one block per CU, 2^28 values would give a lane more than 1024
+    vectors: the launch raises the grid so that every lane's fp64 digit sums stay exact."""
+    n = (1 << 28) + 5
+    # 3.984375 = 255 * 2^-6 is the largest term of its digit (255 << 31 units): 2^14 of them in one
+    # lane's fp64 sum would round, 8192 do not
+    x = torch.full((n,), 3.984375, dtype=torch.bfloat16, device=gpu())
+    exact = n * 3.984375
+    b = hdc.tuning_bucket(n)
+    old = hdc.get_tuning(hdc.OP_TRANSFORM_REDUCE, hdc.BF16, hdc.ACC_EXACT, b)
+    try:
+        hdc.set_tuning(hdc.OP_TRANSFORM_REDUCE, hdc.BF16, hdc.ACC_EXACT, b, block=64, unroll=1, grid_mult=1)
+        assert hdc.transform_reduce(x, {"fn": "identity"}, "exact").item() == exact
+    finally:
+        hdc.set_tuning(hdc.OP_TRANSFORM_REDUCE, hdc.BF16, hdc.ACC_EXACT, b, **old)
