@@ -129,13 +129,15 @@ __global__ __launch_bounds__(1024) void exact_bf16_kernel(const uint16_t* __rest
     bool special = false;
 #pragma unroll
     for (int i = 0; i < V; ++i) {
-      const uint32_t E = (u[i] >> 7) & 0xFFu, M = u[i] & 0x7Fu;
+      const uint32_t E = (u[i] >> 7) & 0xFFu;
       special = special || E == 0xFFu;
-      const int32_t m = E == 0xFFu ? 0 : (int32_t)(E ? (M | 0x80u) : M);
-      const uint32_t q = E ? E - 1 : 0;
-      t[i] = __builtin_ldexp((double)((u[i] >> 15) ? -m : m), (int)(q & 31u));  // exact
+      const uint32_t q = (E > 1u ? E : 1u) - 1u;  // E - 1, or 0 for subnormals
       d[i] = (int)(q >> 5);
-      mine |= m ? 1u << d[i] : 0u;
+      // the value itself (bf16 is the top half of binary32; subnormals are kept),
+      // scaled by 2^(133 - 32 d): the signed integer m 2^(q mod 32), exact in fp64
+      const float v = __builtin_bit_cast(float, (E == 0xFFu ? 0u : u[i]) << 16);
+      t[i] = __builtin_ldexp((double)v, 133 - 32 * d[i]);
+      mine |= v != 0.0f ? 1u << d[i] : 0u;
     }
     if (__builtin_amdgcn_ballot_w64(special) != 0) {  // rare: infinities and NaNs present
 #pragma unroll
