@@ -90,10 +90,10 @@ void host_map(const F& f, const void* x, void* y, int64_t n, int32_t nthreads) {
 }
 
 // The array is cut into blocks of kHostBlock elements from its start; the
-// threads fold disjoint runs of whole blocks, and the block states are then
-// merged in block order by one thread (plain: fp32; compensated: fp64 of
-// s + c; integers: wrapping).  So the result does not depend on the thread
-// count.
+// threads fold disjoint runs of whole blocks, and one thread then merges the
+// block states in a fixed order (plain: a pairwise tree in fp32;
+// compensated: fp64 of s + c in block order; integers: wrapping).  So the
+// result does not depend on the thread count.
 template <class F, class S, class Acc>
   requires host_callable<F>
 void host_reduce(const F& f, const void* x, const void* z, int64_t n, void* out, int32_t nthreads) {
@@ -111,9 +111,13 @@ void host_reduce(const F& f, const void* x, const void* z, int64_t n, void* out,
     double t = 0.0;
     for (const Acc& a : blk) t += __builtin_isfinite(a.s) ? (double)a.s + (double)a.c : (double)a.s;
     *static_cast<double*>(out) = t;
-  } else {
-    Acc total = Acc::zero();
-    for (const Acc& a : blk) total = Acc::merge(total, a);
+  } else {  // pairwise in a fixed tree over the blocks: short fp32 chains for any n
+    for (size_t w = blk.size(); w > 1; w = (w + 1) / 2)
+      for (size_t i = 0; i < w / 2; ++i) {
+        blk[i] = Acc::merge(blk[2 * i], blk[2 * i + 1]);
+        if (w % 2 && i + 1 == w / 2) blk[i + 1] = blk[w - 1];  // an odd last block moves up alone
+      }
+    const Acc total = blk.empty() ? Acc::zero() : blk[0];
     if constexpr (std::is_same_v<Acc, PlainAcc>)
       *static_cast<float*>(out) = total.s;
     else
