@@ -2,9 +2,11 @@
 // kernels, as the denominator check for the library's roofline fractions.
 //
 // Read-only and copy kernels over 1 GiB of 16-byte vectors, each with the
-// default and the non-temporal cache policy, swept over block size and grid;
-// median of 7 timed launches (HIP events) per point.  Prints one line per
-// point and a JSON summary line.  Exit status 0 on success, 1 on a HIP error.
+// default and the non-temporal cache policy, swept over block size and grid,
+// then the copy with every combination of the sc0 / sc1 / nt policy bits on
+// its loads and stores at one geometry; median of 7 timed launches (HIP
+// events) per point.  Prints one line per point and a JSON summary line.
+// Exit status 0 on success, 1 on a HIP error.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -64,6 +66,30 @@ __global__ __launch_bounds__(1024) void copy_kernel(const u32x4* __restrict__ x,
   }
 }
 
+// Copy through buffer instructions with explicit cache-policy bits (gfx950:
+// 1 sc0, 2 nt, 16 sc1) on the loads and on the stores.  1 GiB fits one
+// buffer descriptor; out-of-range accesses would read 0 and drop the store.
+template <int U, int kLoadPolicy, int kStorePolicy>
+__global__ __launch_bounds__(1024) void copy_policy_kernel(const u32x4* x, u32x4* y, int64_t nvec) {
+  const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc((void*)x, 0, 0x7FFFFFFF, 0x00020000);
+  const __amdgpu_buffer_rsrc_t ry = __builtin_amdgcn_make_buffer_rsrc((void*)y, 0, 0x7FFFFFFF, 0x00020000);
+  const int64_t B = blockDim.x, stride = (int64_t)gridDim.x * B * U;
+  for (int64_t base = (int64_t)blockIdx.x * B * U + threadIdx.x; base < nvec; base += stride) {
+    u32x4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = base + u * B;
+      if (i < nvec)
+        v[u] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rx, (int)(i * 16), 0, kLoadPolicy));
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = base + u * B;
+      if (i < nvec) __builtin_amdgcn_raw_buffer_store_b128(v[u], ry, (int)(i * 16), 0, kStorePolicy);
+    }
+  }
+}
+
 template <class Launch>
 static int median_ms(Launch launch, float* out) {
   hipEvent_t a, b;
@@ -117,6 +143,28 @@ int main() {
                   block, g, r[0], r[1], r[2], r[3], r[4]);
       std::fflush(stdout);
     }
+  }
+  // Cache-policy sweep of the copy at 1024 threads and 32 blocks per CU.
+  {
+    const unsigned g = (unsigned)(cus * 32);
+    float t;
+#define HBM_POLICY(L, S)                                                                                    \
+  do {                                                                                                      \
+    if (median_ms([&] { copy_policy_kernel<8, L, S><<<g, 1024>>>(x, y, nvec); }, &t)) return 1;             \
+    std::printf("copy policy load %2d store %2d: %.0f GB/s\n", L, S, 2 * gb / t);                           \
+    std::fflush(stdout);                                                                                    \
+  } while (0)
+    HBM_POLICY(2, 2);
+    HBM_POLICY(2, 0);
+    HBM_POLICY(2, 1);
+    HBM_POLICY(2, 3);
+    HBM_POLICY(2, 16);
+    HBM_POLICY(2, 17);
+    HBM_POLICY(2, 18);
+    HBM_POLICY(0, 2);
+    HBM_POLICY(3, 2);
+    HBM_POLICY(18, 2);
+#undef HBM_POLICY
   }
   float tm = 0;
   if (median_ms([&] { (void)hipMemcpyAsync(y, x, bytes, hipMemcpyDeviceToDevice, 0); }, &tm)) return 1;
