@@ -166,7 +166,7 @@ class Case:
 
 
 def candidates(op, quick=False):
-    blocks = [256, 512, 1024] if quick else [128, 256, 512, 1024]
+    blocks = [256, 512, 1024] if quick else [64, 128, 256, 512, 1024]
     unrolls = [2, 4, 8] if quick else [1, 2, 4, 8]
     gms = [4, 8, 16] if quick else [2, 4, 8, 16, 32, 64]
     base = [dict(block=b, unroll=u, grid_mult=g) for b, u, g in itertools.product(blocks, unrolls, gms)]
@@ -178,7 +178,7 @@ def candidates(op, quick=False):
         return base
     seg = [dict(chunk=c, small_seg=s, seg_per_wave=w)
            for c, s, w in itertools.product([2048, 4096, 8192] if quick else [1024, 2048, 4096, 8192, 16384],
-                                            [64, 128, 256, 512], [2, 4, 8, 16])]
+                                            [64, 128, 256, 512], [2, 4, 8, 16] if quick else [1, 2, 4, 8, 16, 32, 64])]
     # two stages: geometry at the default segment split, then the split at the best geometry
     return base, seg
 
