@@ -247,7 +247,8 @@ def default_cases(dev, quick=False, log2n=28):
     sizes = synth.call_sizes(synth.seed_of(5))
     cases += [Case(OP_BATCH, F16, ACC_COMPENSATED, sum(sizes[0::2]) // 32, dev, sizes[0::2]),
               Case(OP_BATCH, I32, ACC_EXACT_INT, sum(sizes[1::2]) // 32, dev, sizes[1::2])]
-    cases += [Case(OP_SCAN, F32, ACC_PLAIN, n, dev), Case(OP_SCAN, I32, ACC_EXACT_INT, n, dev)]
+    cases += [Case(OP_SCAN, F32, ACC_PLAIN, n, dev), Case(OP_SCAN, F32, ACC_COMPENSATED, n, dev),
+              Case(OP_SCAN, I32, ACC_EXACT_INT, n, dev)]
     # batched calls: every size bucket of the fused map + reduce
     for m in ([1 << 14, 1 << 18, 1 << 22, 1 << 25] if not quick else [1 << 18, 1 << 25]):
         cases += [Case(OP_MAP_REDUCE, F16, ACC_COMPENSATED, m, dev), Case(OP_MAP_REDUCE, I32, ACC_EXACT_INT, m, dev),

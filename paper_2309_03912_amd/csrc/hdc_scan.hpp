@@ -325,8 +325,13 @@ struct ScanWave {
   // when a lane's run is exactly 16 bytes, so a wavefront's store covers whole
   // lines; cached otherwise, so the cache merges the interleaved runs of a
   // chunk into whole lines).
+  // With 32 output bytes per lane and chunk (V = 2 PER), a whole chunk goes
+  // through the wavefront's 2 KiB `stage` (LDS): each lane writes its 32
+  // bytes, then takes the 16-byte pieces at lanes l and 64 + l of the
+  // chunk's output, so that each non-temporal store instruction of the
+  // wavefront covers one contiguous KiB.
   template <bool kOutAligned>
-  __device__ void emit(const F& f, const Acc& before, int exclusive, OutT* y) const {
+  __device__ void emit(const F& f, const Acc& before, int exclusive, OutT* y, u32x4* stage) const {
     constexpr int PER = 16 / sizeof(OutT);
     bool full = kOutAligned && wbase + 64 * kScanE <= n;
     if constexpr (kSeg) full = full && wbase >= out_lo && wbase + 64 * kScanE <= out_hi;
@@ -341,15 +346,29 @@ struct ScanWave {
         o[e] = exclusive ? prev : ScanOut<Acc>::value(a);
       }
       if (full) {
+        if constexpr (V == 2 * PER) {
+          u32x4 w0, w1;
+          __builtin_memcpy(&w0, &o[0], 16);
+          __builtin_memcpy(&w1, &o[PER], 16);
+          stage[2 * lane] = w0;
+          stage[2 * lane + 1] = w1;
+          __builtin_amdgcn_wave_barrier();
+          const u32x4 r0 = stage[lane], r1 = stage[64 + lane];
+          __builtin_amdgcn_wave_barrier();  // the next chunk's writes come after these reads
+          u32x4* p = reinterpret_cast<u32x4*>(y + index(q, 0) - (int64_t)lane * V);  // the chunk's start
+          __builtin_nontemporal_store(r0, p + lane);
+          __builtin_nontemporal_store(r1, p + 64 + lane);
+        } else {
 #pragma unroll
-        for (int h = 0; h < V / PER; ++h) {
-          u32x4 w;
-          __builtin_memcpy(&w, &o[h * PER], 16);
-          u32x4* p = reinterpret_cast<u32x4*>(y + index(q, h * PER));
-          if constexpr (V == PER)
-            __builtin_nontemporal_store(w, p);
-          else
-            *p = w;
+          for (int h = 0; h < V / PER; ++h) {
+            u32x4 w;
+            __builtin_memcpy(&w, &o[h * PER], 16);
+            u32x4* p = reinterpret_cast<u32x4*>(y + index(q, h * PER));
+            if constexpr (V == PER)
+              __builtin_nontemporal_store(w, p);
+            else
+              *p = w;
+          }
         }
       } else {
 #pragma unroll
@@ -398,6 +417,12 @@ __device__ __forceinline__ ScanWave<F, S, Acc> scan_wave_at(int64_t tile, int64_
 // Then each wavefront takes its lanes' bits (ScanWave::take_heads).  Empty
 // segments repeat a boundary, which sets the same bit again.
 constexpr int kTileWords = 1024 * kScanE / 32;  // bitmap words of the largest tile
+
+// 16-byte vectors of output staging per block: 2 KiB per wavefront when a
+// lane's outputs of a chunk are 32 bytes, none otherwise.
+template <class S, class Acc>
+constexpr int kStageVecs =
+    S::kVec * sizeof(typename ScanOut<Acc>::T) == 32 ? kMaxWaves * 128 : 1;
 
 template <class W>
 __device__ void tile_heads(W& w, const SegSpec& seg, int64_t t0, int64_t len, uint32_t* bits, int64_t* first) {
@@ -484,6 +509,7 @@ __global__ __launch_bounds__(1024) void scan_tiles_kernel(F f, const elem_t<S>* 
   __shared__ Acc lds[kMaxWaves];
   __shared__ uint32_t heads_sh[IsSeg<Acc>::value ? kTileWords : 1];
   __shared__ int64_t first_sh;
+  __shared__ u32x4 stage_sh[kStageVecs<S, Acc>];
   auto w = scan_wave_at<F, S, Acc>(blockIdx.x, n);
   w.template load<kAligned>(x, seg);
   if constexpr (IsSeg<Acc>::value)
@@ -491,7 +517,8 @@ __global__ __launch_bounds__(1024) void scan_tiles_kernel(F f, const elem_t<S>* 
   w.fold(f);
   Acc total;
   const Acc before = block_wave_prefix(w.wave_total, lds, &total);
-  w.template emit<kOutAligned>(f, Acc::merge(offsets[blockIdx.x], before), exclusive, y);
+  w.template emit<kOutAligned>(f, Acc::merge(offsets[blockIdx.x], before), exclusive, y,
+                               stage_sh + (threadIdx.x >> 6) * 128);
 }
 
 // ---------------------------------------------------------------------------
@@ -779,6 +806,7 @@ scan_onepass_kernel(F f, const elem_t<S>* x, int64_t n, SegSpec seg,
   __shared__ uint32_t slots[kTreeLevels * C::kWords * 64];
   __shared__ uint32_t heads_sh[IsSeg<Acc>::value ? kTileWords : 1];
   __shared__ int64_t first_sh;
+  __shared__ u32x4 stage_sh[kStageVecs<S, Acc>];
   if (threadIdx.x == 0) tile_sh = (int64_t)atomicAdd(lb.ticket, 1u);
   __syncthreads();
   const int64_t tile = tile_sh;
@@ -794,7 +822,8 @@ scan_onepass_kernel(F f, const elem_t<S>* x, int64_t n, SegSpec seg,
     if (threadIdx.x == 0) carry_sh = carry;
   }
   __syncthreads();
-  w.template emit<kOutAligned>(f, Acc::merge(C::to(carry_sh), before), exclusive, y);
+  w.template emit<kOutAligned>(f, Acc::merge(C::to(carry_sh), before), exclusive, y,
+                               stage_sh + (threadIdx.x >> 6) * 128);
 }
 
 }  // namespace hdc
