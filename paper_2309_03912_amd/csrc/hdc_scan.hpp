@@ -4,8 +4,9 @@
 // Layout of a tile: wavefront w owns the 64 * kScanE contiguous elements
 // starting at w * 64 * kScanE, as Q = kScanE / V chunks of 64 * V elements
 // (V = elements per 16-byte vector).  In chunk q, lane l owns the V elements
-// at q * 64 V + l V: every load and store of a wavefront covers one
-// contiguous 1-KiB span.  The fold order inside a tile is fixed: a lane folds
+// at q * 64 V + l V: every load of a wavefront covers one contiguous 1-KiB
+// span, and so does every store when a lane's outputs of a chunk take 16
+// bytes, or 32 (through an LDS stage).  The fold order inside a tile is fixed: a lane folds
 // its V terms in order, a wavefront scans the lane totals of each chunk and
 // chains its chunks, the block scans the wavefront totals in wave order.
 //
