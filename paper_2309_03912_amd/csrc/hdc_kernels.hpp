@@ -246,7 +246,11 @@ __global__ __launch_bounds__(1024) void reduce_kernel(F f, const elem_t<S>* x, c
   const int64_t tid = threadIdx.x;
   constexpr bool kInt = std::is_same_v<S, I32>;
   constexpr bool kBatch = !kInt && !F::binary;  // unary float callables run as one batch
-  constexpr int K = kVector ? S::kVec : U;
+  // Independent fold states per lane.  The exact state is 32 bytes, and
+  // eight of them (one per fp16 of a vector) overflow the register file, so
+  // it keeps two; each fp64 chain then takes at most kFlush * N / 2 <= 256
+  // terms between flushes, far inside the exact state's 2^13.
+  constexpr int K = std::is_same_v<Acc, ExactAcc> ? 2 : (kVector ? S::kVec : U);
   constexpr int N = kVector ? U * S::kVec : U;  // elements per lane per step
   // Two-level fold: `acc` takes the terms of at most kFlush steps, then is
   // merged into `outer`.  A plain fp32 chain then never grows longer than
