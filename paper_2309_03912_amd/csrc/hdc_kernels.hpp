@@ -257,6 +257,9 @@ __global__ __launch_bounds__(1024) void reduce_kernel(F f, const elem_t<S>* x, c
   // kFlush * U terms plus one term per kFlush steps, whatever the grid size,
   // which keeps its rounding error far below the tolerance.
   constexpr int kFlush = 8;
+  // A step adds at most ceil(N / K) terms to a chain; the head or tail adds one.
+  static_assert(!std::is_same_v<Acc, ExactAcc> || kFlush * ((N + K - 1) / K) + 1 <= (1 << 13),
+                "an exact fp64 chain must stay within 2^13 terms between flushes");
   Acc acc[K], outer[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = outer[k] = Acc::zero();
