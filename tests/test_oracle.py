@@ -193,6 +193,94 @@ def test_horner_degree_edge_cases():
     assert oracle.term_f32({"fn": "horner", "coef": c}, -0.5) == 2.0 ** -16
 
 
+def _rn_f32(q: Fraction) -> float:
+    """The binary32 value nearest to the rational q, ties to even (IEEE 754
+    roundTiesToEven), with gradual underflow and overflow to infinity.
+    Written from the format's definition: 24-bit significands, exponents
+    -126..127, quantum 2^(max(e, -126) - 23) for 2^e <= |q| < 2^(e+1)."""
+    if q == 0:
+        return 0.0
+    sign = -1 if q < 0 else 1
+    m = abs(q)
+    e = m.numerator.bit_length() - m.denominator.bit_length()
+    if m < Fraction(2) ** e:
+        e -= 1
+    assert Fraction(2) ** e <= m < Fraction(2) ** (e + 1)
+    quantum = Fraction(2) ** (max(e, -126) - 23)
+    scaled = m / quantum
+    k = scaled.numerator // scaled.denominator
+    rem = scaled - k
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and k % 2 == 1):
+        k += 1
+    v = k * quantum
+    if v >= Fraction(2) ** 128:
+        return sign * math.inf
+    return sign * float(v)  # v is a binary32 value, so float() is exact
+
+
+def test_rn_f32_matches_numpy_on_doubles():
+    # the rounding helper itself: every double rounds to binary32 exactly as
+    # numpy's (IEEE) conversion does, subnormals and overflow included
+    rng = np.random.default_rng(3)
+    v = rng.integers(0, 1 << 64, 20000, dtype=np.uint64).view(np.float64)
+    v = v[np.isfinite(v) & (np.abs(v) < 3.5e38)]
+    v = np.concatenate([v, rng.normal(size=5000) * 2.0 ** rng.integers(-160, 120, 5000),
+                        np.array([2.0 ** -150, 3 * 2.0 ** -151, 2.0 ** -149 * 1.5, 3.4028235677973366e38])])
+    with np.errstate(over="ignore"):
+        ref = v.astype(np.float32).astype(np.float64)
+    for x, r in zip(v.tolist(), ref.tolist()):
+        assert _rn_f32(Fraction(x)) == r, x
+
+
+def _horner_one_rounding(coef, x):
+    acc = Fraction(np.float32(coef[-1]).item())
+    xf = Fraction(x)
+    for c in reversed(coef[:-1]):
+        acc = Fraction(_rn_f32(acc * xf + Fraction(np.float32(c).item())))
+    return float(acc)
+
+
+def _horner_two_roundings(coef, x):
+    acc = Fraction(np.float32(coef[-1]).item())
+    xf = Fraction(x)
+    for c in reversed(coef[:-1]):
+        acc = Fraction(_rn_f32(Fraction(_rn_f32(acc * xf)) + Fraction(np.float32(c).item())))
+    return float(acc)
+
+
+def test_horner_rounding_sequence_is_one_fma_per_step():
+    # The fp32 Horner term is acc = c_d, then acc = RN(acc * x + c_k) for
+    # k = d-1 .. 0: one rounding per step (a fused multiply-add).  Emulated
+    # exactly in rational arithmetic with the rounding above, for the
+    # workload's coefficients and for random coefficients of every degree
+    # 0..16.  A multiply and a separate add (two roundings) differ on many of
+    # these points, so that reading of the oracle would fail here.
+    rng = np.random.default_rng(17)
+    xs = np.concatenate([rng.uniform(-1, 1, 1500), rng.uniform(-4, 4, 300)]).astype(np.float32)
+    differs = 0
+    for x in xs.tolist():
+        want = _horner_one_rounding(COEF8, x)
+        assert oracle.term_f32(HORNER, x) == want, x
+        differs += _horner_two_roundings(COEF8, x) != want
+    assert differs > 100  # the test separates one rounding from two
+    for d in range(0, 17):
+        coef = (rng.normal(size=d + 1) * 2.0 ** rng.integers(-6, 6, d + 1)).astype(np.float32).tolist()
+        spec = {"fn": "horner", "coef": coef}
+        for x in rng.uniform(-1.5, 1.5, 60).astype(np.float32).tolist():
+            assert oracle.term_f32(spec, x) == _horner_one_rounding(coef, x), (d, x)
+
+
+def test_horner_fp64_rounding_sequence():
+    # fp64 Horner (the sequential fp64 reference's terms): one rounding to
+    # binary64 per step; float(Fraction) rounds correctly to nearest-even.
+    rng = np.random.default_rng(19)
+    for x in rng.uniform(-2, 2, 400).tolist():
+        acc = Fraction(np.float32(COEF8[-1]).item())
+        for c in reversed(COEF8[:-1]):
+            acc = Fraction(float(acc * Fraction(x) + Fraction(np.float32(c).item())))
+        assert oracle.term_f64(HORNER, x) == float(acc), x
+
+
 def test_affine_map_f32_single_rounding():
     x = synth.uniform_pm1_f32(1, 0, 4096)
     x = torch.cat([x, torch.tensor([3.4e38, -3.4e38, 1e-45, 0.1, 1 / 3], dtype=torch.float32)])
