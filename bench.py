@@ -523,14 +523,17 @@ def form_scan(args, torch, hdc, synth):
     hor = hdc.horner(synth.horner_coefficients(8))
     y = torch.empty(n, dtype=torch.float32, device=dev)
     ws = hdc.workspace(dev, hdc.OP_SCAN, hdc.F32, hdc.ACC_PLAIN, n)
-    t = ev_time(torch, lambda: hdc.scan(x, hor, "plain", out=y, ws=ws))
+    t = ev_time(torch, lambda: hdc.scan(x, hor, "plain", out=y, ws=ws, check=False))
+    ok = hdc.scan_status(ws) == 0  # the last timed call's output is valid
     xi = synth.uniform_int(synth.seed_of(2), synth.STREAM["xi"], n, 20, dev)
     yi = torch.empty(n, dtype=torch.int64, device=dev)
     wsi = hdc.workspace(dev, hdc.OP_SCAN, hdc.I32, hdc.ACC_EXACT_INT, n)
-    ti = ev_time(torch, lambda: hdc.scan(xi, hdc.identity(), "exact_int", out=yi, ws=wsi))
+    ti = ev_time(torch, lambda: hdc.scan(xi, hdc.identity(), "exact_int", out=yi, ws=wsi, check=False))
+    ok = ok and hdc.scan_status(wsi) == 0
     res = {"n": n, "f32_horner_ms": round(t, 5), "f32_horner_GBps": round(gbps(8 * n, t), 1),
            "i32_to_i64_ms": round(ti, 5), "i32_to_i64_GBps": round(gbps(12 * n, ti), 1),
-           "bytes_per_element": "algorithmic: f32 4 read + 4 write; i32->i64 4 read + 8 write"}
+           "bytes_per_element": "algorithmic: f32 4 read + 4 write; i32->i64 4 read + 8 write",
+           "status_ok": bool(ok)}
     del x, y, xi, yi
     torch.cuda.empty_cache()
     # segmented scan over the segmented form's 100,000 lognormal segments
@@ -542,9 +545,10 @@ def form_scan(args, torch, hdc, synth):
     ys = torch.empty(m, dtype=torch.float32, device=dev)
     offg = off.to(dev)
     wss = hdc.workspace(dev, hdc.OP_SCAN, hdc.F32, hdc.ACC_PLAIN, m)
-    ts = ev_time(torch, lambda: hdc.segmented_scan(xs, offg, hor, "plain", out=ys, ws=wss))
+    ts = ev_time(torch, lambda: hdc.segmented_scan(xs, offg, hor, "plain", out=ys, ws=wss, check=False))
     res["segmented_100k_lognormal"] = {"elements": m, "segments": int(L.numel()), "f32_horner_ms": round(ts, 5),
-                                       "GBps": round(gbps(8 * m + 8 * (L.numel() + 1), ts), 1)}
+                                       "GBps": round(gbps(8 * m + 8 * (L.numel() + 1), ts), 1),
+                                       "status_ok": hdc.scan_status(wss) == 0}
     del xs, ys
     torch.cuda.empty_cache()
     return res

@@ -117,24 +117,40 @@ typedef struct hdc_functor {
 
 /*
  * y[i] = f(x[i]) for 0 <= i < n, written in x's storage type.
+ *   The operation is the paper's kernel that takes a callable by value and
+ *   applies it once per element in every device thread (section 2.4, listing
+ *   lst_solution_ifdef_cudaarch; one callable for both sides, section 2.6,
+ *   listing lst_solution_exp_constexpr_la); `f` is that callable, chosen from
+ *   the closed set of hdc_fn (section 2.10: the type decides the overload).
  *   Floats: f evaluated in fp32 on the exactly widened input; fp16 / bf16
  *   results are rounded to nearest-even.  IDENTITY copies bits.
  *   Supported: IDENTITY, AFFINE on F32/F16/BF16/I32; HORNER on F32/F16/BF16.
- *   x == y (in place) is allowed; partial overlap is rejected.  n == 0 is a
- *   no-op.  Bytes moved: 2 n sizeof(element).
+ *   x, y: device arrays of n elements, caller-owned.  x == y (in place) is
+ *   allowed; partial overlap is rejected.  n == 0 is a no-op.  Errors:
+ *   HDC_ERR_INVALID_ARGUMENT (NULL with n > 0, misaligned element, n < 0,
+ *   overlap), HDC_ERR_UNSUPPORTED (functor / dtype pair not provided).
+ *   Bytes moved: 2 n sizeof(element).
  */
 hdc_status hdc_map(const hdc_functor* f, hdc_dtype dt, const void* x, void* y,
                    int64_t n, void* stream);
 
 /*
  * out = sum_i f(x[i])  (PRODUCT: sum_i x[i] * z[i], z of the same dtype).
+ *   The callable applied per element as in hdc_map (section 2.4, listing
+ *   lst_solution_ifdef_cudaarch), its results folded into one sum.
  *   acc PLAIN or COMPENSATED for F32/F16/BF16, EXACT_INT for I32 (IDENTITY
  *   or AFFINE).  n == 0 writes 0.  The summation order is fixed by (n, the
  *   tuning in force): results are bit-reproducible run to run, but a
  *   different tuning may change the last bits of a floating-point result.
+ *   x, z: device arrays of n elements; out: one device float (PLAIN), double
+ *   (COMPENSATED, EXACT) or int64 (EXACT_INT), all caller-owned.
  *   workspace: device scratch of at least hdc_workspace_size(...) bytes, or
  *   NULL to use a library-owned buffer (per device and stream, grown outside
- *   graph capture only).  Bytes moved: n sizeof(element) (x2 for PRODUCT).
+ *   graph capture only).  Errors: HDC_ERR_INVALID_ARGUMENT (NULL or
+ *   misaligned pointers, n < 0), HDC_ERR_UNSUPPORTED (functor / dtype /
+ *   accumulation not provided), HDC_ERR_WORKSPACE (workspace too small, or
+ *   the library buffer would have to grow under capture).
+ *   Bytes moved: n sizeof(element) (x2 for PRODUCT).
  */
 hdc_status hdc_transform_reduce(const hdc_functor* f, hdc_dtype dt,
                                 const void* x, const void* z, int64_t n,
@@ -143,6 +159,10 @@ hdc_status hdc_transform_reduce(const hdc_functor* f, hdc_dtype dt,
 
 /*
  * out[j] = sum_{offsets[j] <= i < offsets[j+1]} f(x[i]) for 0 <= j < S.
+ *   The per-element callable as in hdc_transform_reduce (section 2.4,
+ *   listing lst_solution_ifdef_cudaarch), folded separately over each of
+ *   many uneven segments in one batch.
+ *   x: device array of at least offsets[S] elements.
  *   offsets: device int64 array of S+1 entries, non-decreasing, offsets[0] >= 0
  *   (a precondition, not checked per call: checking it would need a device
  *   round trip; hdc_validate_offsets checks it synchronously).
@@ -150,13 +170,26 @@ hdc_status hdc_transform_reduce(const hdc_functor* f, hdc_dtype dt,
  *   Empty segments give 0.  The whole batch is one plan pass, one
  *   persistent pass and one combine pass, with no host synchronisation.
  *   IDENTITY, AFFINE, HORNER as for transform_reduce (no PRODUCT).
- *   `total` is an upper bound on offsets[S] (used to size the work list).
+ *   workspace: at least hdc_workspace_size(HDC_OP_SEGMENTED_REDUCE, dt, acc,
+ *   total, S) bytes for a total >= offsets[S]; its size sets the capacity
+ *   of the work lists.  If the segments need more than ws_bytes holds
+ *   (offsets[S] above the total it was sized for), the call still returns
+ *   the correct sums, folding every segment whole with one wavefront
+ *   (slower, and the last bits of a floating-point sum may differ).  The
+ *   size bucket of the tuning is that of the largest total ws_bytes serves.
+ *   NULL: the library's buffer, sized from offsets[S], which the call then
+ *   reads from the device (a synchronous 8-byte copy on `stream`; refused
+ *   with HDC_ERR_WORKSPACE under graph capture).
+ *   Errors: HDC_ERR_INVALID_ARGUMENT (S < 0 or >= 2^31 - 1, NULL or
+ *   misaligned offsets / out, misaligned x or workspace),
+ *   HDC_ERR_UNSUPPORTED (functor / dtype / accumulation not provided),
+ *   HDC_ERR_WORKSPACE (ws_bytes below the bound for S segments).
  */
 hdc_status hdc_segmented_reduce(const hdc_functor* f, hdc_dtype dt,
                                 const void* x, const int64_t* offsets,
-                                int64_t num_segments, int64_t total,
-                                hdc_accum acc, void* out, void* workspace,
-                                size_t ws_bytes, void* stream);
+                                int64_t num_segments, hdc_accum acc,
+                                void* out, void* workspace, size_t ws_bytes,
+                                void* stream);
 
 /*
  * Fused map + transform_reduce: y[i] = f(x[i]) as hdc_map, and
@@ -180,10 +213,9 @@ hdc_status hdc_map_reduce(const hdc_functor* f, const hdc_functor* g,
  *    tree (the last tile of a group also the group's node), and folds its
  *    carry from at most 63 nodes per tree level, in a fixed order.  The carry between tiles is
  *    fp64 for floats and int64 for integers.  x is read once.  A small
- *    clear kernel runs first on the same stream.  The 32-bit word at byte 4
- *    of the workspace is nonzero after the call if a wait for an earlier
- *    tile gave up; the output is then invalid.  Tiles start in order, so a
- *    give-up is not expected.
+ *    clear kernel runs first on the same stream.  Every wait is bounded:
+ *    if one gives up, the call's output is invalid and hdc_scan_status
+ *    reports it.  Tiles start in order, so a give-up is not expected.
  *  - 1: three passes (tile sums, tile offsets, tile scans) with no waiting
  *    between blocks.  x is read twice.
  * Results are bit-reproducible for a fixed tuning.
@@ -212,6 +244,20 @@ hdc_status hdc_segmented_scan(const hdc_functor* f, hdc_dtype dt, const void* x,
                               int64_t total, void* y, hdc_accum acc,
                               int32_t exclusive, void* workspace,
                               size_t ws_bytes, void* stream);
+
+/*
+ * Status of the last hdc_scan or hdc_segmented_scan that ran with this
+ * workspace (NULL: the library's buffer of the current device and
+ * `stream`): copies one int32 into *status, stream-ordered and
+ * asynchronous (a device pointer, or pinned host memory read after the
+ * stream is synchronised).  0: the scan's output is valid; nonzero: a wait
+ * of the single-pass schedule for an earlier tile gave up and that output
+ * is invalid (run it again).  Calls that launch nothing (n == 0) leave the
+ * word as it was.  Errors: HDC_ERR_INVALID_ARGUMENT (status NULL, no
+ * library buffer for this stream, misaligned workspace), HDC_ERR_HIP.
+ */
+hdc_status hdc_scan_status(const void* workspace, int32_t* status,
+                           void* stream);
 
 /* One call of a grouped batch (device pointers). */
 typedef struct hdc_batch_call {

@@ -41,7 +41,7 @@ FN = {"identity": FN_IDENTITY, "affine": FN_AFFINE, "horner": FN_HORNER, "produc
 # Every symbol include/hdc.h declares.
 EXPORTS = [
     "hdc_map", "hdc_transform_reduce", "hdc_segmented_reduce", "hdc_map_reduce", "hdc_batch_map_reduce",
-    "hdc_host_map", "hdc_host_transform_reduce", "hdc_scan", "hdc_segmented_scan",
+    "hdc_host_map", "hdc_host_transform_reduce", "hdc_scan", "hdc_segmented_scan", "hdc_scan_status",
     "hdc_workspace_size", "hdc_validate_offsets", "hdc_set_tuning", "hdc_get_tuning",
     "hdc_load_tuning", "hdc_tuning_bucket", "hdc_status_string", "hdc_last_error", "hdc_version",
 ]
@@ -88,7 +88,7 @@ def lib() -> ctypes.CDLL:
         st = ctypes.c_int
         L.hdc_map.argtypes = [P(Functor), i32, vp, vp, i64, vp]
         L.hdc_transform_reduce.argtypes = [P(Functor), i32, vp, vp, i64, i32, vp, vp, ctypes.c_size_t, vp]
-        L.hdc_segmented_reduce.argtypes = [P(Functor), i32, vp, vp, i64, i64, i32, vp, vp, ctypes.c_size_t, vp]
+        L.hdc_segmented_reduce.argtypes = [P(Functor), i32, vp, vp, i64, i32, vp, vp, ctypes.c_size_t, vp]
         L.hdc_map_reduce.argtypes = [P(Functor), P(Functor), i32, vp, vp, i64, i32, vp, vp, ctypes.c_size_t, vp]
         L.hdc_batch_map_reduce.argtypes = [P(Functor), P(Functor), i32, i32, P(BatchCall), ctypes.c_int32, vp,
                                            ctypes.c_size_t, vp]
@@ -97,6 +97,7 @@ def lib() -> ctypes.CDLL:
         L.hdc_scan.argtypes = [P(Functor), i32, vp, vp, i64, i32, ctypes.c_int32, vp, ctypes.c_size_t, vp]
         L.hdc_segmented_scan.argtypes = [P(Functor), i32, vp, vp, i64, i64, vp, i32, ctypes.c_int32, vp,
                                          ctypes.c_size_t, vp]
+        L.hdc_scan_status.argtypes = [vp, vp, vp]
         L.hdc_workspace_size.argtypes = [i32, i32, i32, i64, i64, P(ctypes.c_size_t)]
         L.hdc_validate_offsets.argtypes = [vp, i64, i64, vp]
         L.hdc_set_tuning.argtypes = [i32, i32, i32, i32, P(Tuning)]
@@ -105,8 +106,8 @@ def lib() -> ctypes.CDLL:
         L.hdc_load_tuning.argtypes = [ctypes.c_char_p]
         for name in ["hdc_map", "hdc_transform_reduce", "hdc_segmented_reduce", "hdc_map_reduce",
                      "hdc_batch_map_reduce", "hdc_host_map", "hdc_host_transform_reduce", "hdc_scan",
-                     "hdc_segmented_scan", "hdc_workspace_size", "hdc_validate_offsets", "hdc_set_tuning", "hdc_get_tuning",
-                     "hdc_load_tuning", "hdc_tuning_bucket"]:
+                     "hdc_segmented_scan", "hdc_scan_status", "hdc_workspace_size", "hdc_validate_offsets",
+                     "hdc_set_tuning", "hdc_get_tuning", "hdc_load_tuning", "hdc_tuning_bucket"]:
             getattr(L, name).restype = st
         L.hdc_status_string.argtypes = [st]
         L.hdc_status_string.restype = ctypes.c_char_p
@@ -266,9 +267,10 @@ def map_reduce(x: torch.Tensor, map_fn, reduce_fn, acc="plain", out: torch.Tenso
     return y, r
 
 
-def segmented_reduce(x: torch.Tensor, offsets: torch.Tensor, fn, acc="plain", total: int | None = None,
+def segmented_reduce(x: torch.Tensor, offsets: torch.Tensor, fn, acc="plain",
                      out: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
-    """out[j] = sum_{offsets[j] <= i < offsets[j+1]} fn(x[i]) for every segment j."""
+    """out[j] = sum_{offsets[j] <= i < offsets[j+1]} fn(x[i]) for every segment j
+    (offsets[S] <= x.numel(); the default workspace is sized for x.numel())."""
     x = _gpu_tensor(x, "x")
     offsets = _gpu_tensor(offsets, "offsets")
     if offsets.dtype != torch.int64:
@@ -278,12 +280,11 @@ def segmented_reduce(x: torch.Tensor, offsets: torch.Tensor, fn, acc="plain", to
     S = offsets.numel() - 1
     if S < 0:
         raise ValueError("offsets needs at least one entry")
-    total = x.numel() if total is None else int(total)
     r = torch.empty(S, dtype=OUT_DTYPE[a], device=x.device) if out is None else out
     if ws is None:
-        ws = workspace(x.device, OP_SEGMENTED_REDUCE, dt, a, total, S)
+        ws = workspace(x.device, OP_SEGMENTED_REDUCE, dt, a, x.numel(), S)
     f = make_functor(fn)
-    _check(lib().hdc_segmented_reduce(ctypes.byref(f), dt, x.data_ptr(), offsets.data_ptr(), S, total, a,
+    _check(lib().hdc_segmented_reduce(ctypes.byref(f), dt, x.data_ptr(), offsets.data_ptr(), S, a,
                                       r.data_ptr(), ws.data_ptr(), ws.numel(), _stream(x)))
     return r
 
@@ -320,9 +321,27 @@ def batch_map_reduce(xs, map_fn, reduce_fn, acc="plain", ys=None, outs=None, ws=
     return ys, outs
 
 
+def scan_status(ws: torch.Tensor) -> int:
+    """The status word of the last scan run with workspace ``ws`` (hdc_scan_status), read
+    synchronously: 0 = its output is valid, nonzero = a wait gave up and the output is invalid."""
+    st = torch.zeros((), dtype=torch.int32, device=ws.device)
+    _check(lib().hdc_scan_status(ws.data_ptr(), st.data_ptr(), _stream(ws)))
+    return int(st.item())
+
+
+def _check_scan(ws: torch.Tensor, check: bool) -> None:
+    # a synchronous read, skipped while the stream is being captured into a graph
+    if check and not torch.cuda.is_current_stream_capturing():
+        if scan_status(ws) != 0:
+            raise HdcError(ERR_HIP, "a wait of the single-pass scan gave up; the output is invalid")
+
+
 def scan(x: torch.Tensor, fn, acc="plain", exclusive: bool = False, out: torch.Tensor | None = None,
-         ws: torch.Tensor | None = None) -> torch.Tensor:
-    """Prefix sums of fn(x): float32 (plain), float64 (compensated) or int64 (exact_int)."""
+         ws: torch.Tensor | None = None, check: bool = True) -> torch.Tensor:
+    """Prefix sums of fn(x): float32 (plain), float64 (compensated) or int64 (exact_int).
+    ``check`` reads the scan's status word afterwards (a stream synchronisation) and raises
+    HdcError if the single pass gave up; pass False to keep the call asynchronous and read
+    ``scan_status(ws)`` later."""
     x = _gpu_tensor(x, "x")
     a = _acc(acc)
     dt = _dtype(x)
@@ -332,14 +351,17 @@ def scan(x: torch.Tensor, fn, acc="plain", exclusive: bool = False, out: torch.T
     f = make_functor(fn)
     _check(lib().hdc_scan(ctypes.byref(f), dt, x.data_ptr(), y.data_ptr(), x.numel(), a, int(exclusive),
                           ws.data_ptr(), ws.numel(), _stream(x)))
+    if x.numel() > 0:
+        _check_scan(ws, check)
     return y
 
 
 def segmented_scan(x: torch.Tensor, offsets: torch.Tensor, fn, acc="plain", exclusive: bool = False,
                    total: int | None = None, out: torch.Tensor | None = None,
-                   ws: torch.Tensor | None = None) -> torch.Tensor:
+                   ws: torch.Tensor | None = None, check: bool = True) -> torch.Tensor:
     """Prefix sums of fn(x) restarting at every segment start (offsets: int64 CSR on the GPU).
-    Positions outside every segment keep the contents of `out` (zeros when it is allocated here)."""
+    Positions outside every segment keep the contents of `out` (zeros when it is allocated here).
+    ``check`` as for scan()."""
     x = _gpu_tensor(x, "x")
     offsets = _gpu_tensor(offsets, "offsets")
     if offsets.dtype != torch.int64:
@@ -356,6 +378,8 @@ def segmented_scan(x: torch.Tensor, offsets: torch.Tensor, fn, acc="plain", excl
     f = make_functor(fn)
     _check(lib().hdc_segmented_scan(ctypes.byref(f), dt, x.data_ptr(), offsets.data_ptr(), S, total,
                                     y.data_ptr(), a, int(exclusive), ws.data_ptr(), ws.numel(), _stream(x)))
+    if S > 0 and total > 0:
+        _check_scan(ws, check)
     return y
 
 

@@ -9,6 +9,7 @@
 // per element.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -43,7 +44,9 @@ hdc_status fail(hdc_status s, const char* fmt, ...) {
 
 namespace {
 constexpr int kMaxDevices = 64;
-int g_cus[kMaxDevices];  // compute units per device; 0 = not queried yet
+// Compute units per device; 0 = not queried yet.  Concurrent first calls may
+// both query and store the same value, so the accesses are atomic.
+std::atomic<int> g_cus[kMaxDevices];
 }  // namespace
 
 hdc_status compute_units(int* cus) {
@@ -51,13 +54,13 @@ hdc_status compute_units(int* cus) {
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return fail(HDC_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
   if (dev < 0 || dev >= kMaxDevices) return fail(HDC_ERR_HIP, "device index %d out of range", dev);
-  if (g_cus[dev] == 0) {
-    int v = 0;
+  int v = g_cus[dev].load(std::memory_order_relaxed);
+  if (v == 0) {
     e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return fail(HDC_ERR_HIP, "hipDeviceGetAttribute: %s", hipGetErrorString(e));
-    g_cus[dev] = v;
+    g_cus[dev].store(v, std::memory_order_relaxed);
   }
-  *cus = g_cus[dev];
+  *cus = v;
   return HDC_OK;
 }
 
@@ -330,29 +333,51 @@ hdc_status hdc_map_reduce(const hdc_functor* f, const hdc_functor* g, hdc_dtype 
 }
 
 hdc_status hdc_segmented_reduce(const hdc_functor* f, hdc_dtype dt, const void* x, const int64_t* offsets,
-                                int64_t num_segments, int64_t total, hdc_accum acc, void* out, void* workspace,
-                                size_t ws_bytes, void* stream) {
+                                int64_t num_segments, hdc_accum acc, void* out, void* workspace, size_t ws_bytes,
+                                void* stream) {
   HDC_TRY(check_functor(f, dt, false));
   HDC_TRY(check_acc(dt, acc));
   if (acc == HDC_ACC_EXACT) return fail(HDC_ERR_UNSUPPORTED, "EXACT is provided for transform_reduce and map_reduce");
   if (num_segments < 0) return fail(HDC_ERR_INVALID_ARGUMENT, "num_segments is negative");
   if (num_segments >= INT32_MAX) return fail(HDC_ERR_INVALID_ARGUMENT, "more than 2^31 - 2 segments");
-  if (total < 0) return fail(HDC_ERR_INVALID_ARGUMENT, "total is negative");
-  if (total / kMinChunk >= INT32_MAX / 2) return fail(HDC_ERR_INVALID_ARGUMENT, "total is too large");
   if (num_segments == 0) return HDC_OK;
   if (!offsets) return fail(HDC_ERR_INVALID_ARGUMENT, "offsets is NULL");
   if ((uintptr_t)offsets % 8) return fail(HDC_ERR_INVALID_ARGUMENT, "offsets is not 8-byte aligned");
-  HDC_TRY(check_ptr(x, dt, total, "x"));
+  HDC_TRY(check_ptr(x, dt, 0, "x"));
   if (!out) return fail(HDC_ERR_INVALID_ARGUMENT, "out is NULL");
   const size_t osz = acc == HDC_ACC_PLAIN ? 4 : 8;
   if ((uintptr_t)out % osz) return fail(HDC_ERR_INVALID_ARGUMENT, "out is not aligned to its element size");
   hipStream_t st = (hipStream_t)stream;
-  const Tuning t = tuning_for(HDC_OP_SEGMENTED_REDUCE, dt, acc, total);
   void* ws = nullptr;
-  HDC_TRY(resolve_workspace(workspace, ws_bytes, seg_layout(total, num_segments, t.chunk).bytes, st, &ws));
-  if ((uintptr_t)ws % 256) return fail(HDC_ERR_INVALID_ARGUMENT, "workspace is not 256-byte aligned");
-
-  return run_segmented(*f, dt, x, offsets, num_segments, total, acc, out, ws, t, st);
+  size_t cap_bytes = 0;
+  int64_t total_bound = 0;  // the size bucket's element count
+  if (workspace) {
+    if ((uintptr_t)workspace % 256) return fail(HDC_ERR_INVALID_ARGUMENT, "workspace is not 256-byte aligned");
+    if (seg_capacity(ws_bytes, num_segments) < 1)
+      return fail(HDC_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes %lld segments need",
+                  ws_bytes, seg_layout_cap(1, num_segments).bytes, (long long)num_segments);
+    ws = workspace;
+    cap_bytes = ws_bytes;
+    total_bound = seg_total_bound(ws_bytes, num_segments);
+  } else {
+    // The library's buffer is sized from offsets[S], read from the device.
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(st, &cs);
+    if (e != hipSuccess) return fail(HDC_ERR_HIP, "hipStreamIsCapturing: %s", hipGetErrorString(e));
+    if (cs != hipStreamCaptureStatusNone)
+      return fail(HDC_ERR_WORKSPACE, "a segmented reduce under graph capture needs a workspace");
+    int64_t total = 0;
+    e = hipMemcpyAsync(&total, offsets + num_segments, sizeof total, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(HDC_ERR_HIP, "reading offsets[S]: %s", hipGetErrorString(e));
+    if (total < 0 || total / kMinChunk >= INT32_MAX / 2)
+      return fail(HDC_ERR_INVALID_ARGUMENT, "offsets[S] = %lld is out of range", (long long)total);
+    cap_bytes = seg_layout(total, num_segments, kMinChunk).bytes;
+    HDC_TRY(resolve_workspace(nullptr, 0, cap_bytes, st, &ws));
+    total_bound = total;
+  }
+  const Tuning t = tuning_for(HDC_OP_SEGMENTED_REDUCE, dt, acc, total_bound);
+  return run_segmented(*f, dt, x, offsets, num_segments, acc, out, ws, cap_bytes, t, st);
 }
 
 hdc_status hdc_batch_map_reduce(const hdc_functor* f, const hdc_functor* g, hdc_dtype dt, hdc_accum acc,
@@ -386,6 +411,7 @@ hdc_status hdc_batch_map_reduce(const hdc_functor* f, const hdc_functor* g, hdc_
   size_t need = batch_workspace_bytes(total, count);
   if (need < reduce_workspace_bytes()) need = reduce_workspace_bytes();  // calls run one by one reuse it
   HDC_TRY(resolve_workspace(workspace, ws_bytes, need, st, &ws));
+  const size_t cap = workspace ? ws_bytes : need;  // the library's buffer holds at least `need`
 
   // Calls whose x and y disagree in 16-byte alignment run one by one; the
   // rest go in groups of up to kBatchMax calls.
@@ -394,7 +420,7 @@ hdc_status hdc_batch_map_reduce(const hdc_functor* f, const hdc_functor* g, hdc_
   char* wsb = static_cast<char*>(ws);  // groups run in stream order and share it
   auto flush = [&]() -> hdc_status {
     if (ng == 0) return HDC_OK;
-    const hdc_status r = run_batch(f, *g, dt, acc, calls, grp, ng, wsb, t, st);
+    const hdc_status r = run_batch(f, *g, dt, acc, calls, grp, ng, wsb, cap, t, st);
     ng = 0;
     return r;
   };
@@ -489,6 +515,26 @@ hdc_status hdc_segmented_scan(const hdc_functor* f, hdc_dtype dt, const void* x,
   void* ws = nullptr;
   HDC_TRY(resolve_workspace(workspace, ws_bytes, scan_workspace_bytes(total), st, &ws));
   return run_segmented_scan(*f, dt, x, offsets, num_segments, y, total, acc, exclusive, ws, t, st);
+}
+
+hdc_status hdc_scan_status(const void* workspace, int32_t* status, void* stream) {
+  if (!status) return fail(HDC_ERR_INVALID_ARGUMENT, "status is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  const void* ws = workspace;
+  if (!ws) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(HDC_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    std::lock_guard<std::mutex> g(g_ws_mu);
+    auto it = g_ws.find({dev, (void*)stream});
+    if (it == g_ws.end() || !it->second.ptr)
+      return fail(HDC_ERR_INVALID_ARGUMENT, "no library workspace exists for this device and stream");
+    ws = it->second.ptr;
+  }
+  if ((uintptr_t)ws % 256) return fail(HDC_ERR_INVALID_ARGUMENT, "workspace is not 256-byte aligned");
+  const hipError_t e = hipMemcpyAsync(status, static_cast<const char*>(ws) + 4, sizeof(int32_t), hipMemcpyDefault, st);
+  if (e != hipSuccess) return fail(HDC_ERR_HIP, "copying the scan status: %s", hipGetErrorString(e));
+  return HDC_OK;
 }
 
 hdc_status hdc_workspace_size(int op, hdc_dtype dt, hdc_accum acc, int64_t n, int64_t num_segments,

@@ -60,13 +60,14 @@ struct SegLayout {
 };
 
 // Partial slots of a grouped batch: at most total/chunk + count chunks.
-inline size_t batch_workspace_bytes(int64_t total, int64_t count) {
+constexpr size_t batch_workspace_bytes(int64_t total, int64_t count) {
   return round_up((size_t)(total / kMinChunk + count + 1) * kPartialBytes, 256);
 }
 
-inline SegLayout seg_layout(int64_t total, int64_t S, int64_t chunk) {
+// The sections for a full-piece capacity of `cap_full` entries.
+constexpr SegLayout seg_layout_cap(int64_t cap_full, int64_t S) {
   SegLayout l{};
-  l.cap_full = total / chunk + 1;
+  l.cap_full = cap_full;
   l.cap_part = S > 0 ? S : 1;
   l.cap_partials = l.cap_full + l.cap_part;
   l.plan_blocks = (S + kPlanBlock - 1) / kPlanBlock;
@@ -80,6 +81,34 @@ inline SegLayout seg_layout(int64_t total, int64_t S, int64_t chunk) {
   l.partials = o;  o += round_up((size_t)l.cap_partials * kPartialBytes, 256);
   l.bytes = o;
   return l;
+}
+
+// The layout for segments holding at most `total` elements, cut into pieces
+// of `chunk`: at most total / chunk full pieces plus one.
+constexpr SegLayout seg_layout(int64_t total, int64_t S, int64_t chunk) {
+  return seg_layout_cap(total / chunk + 1, S);
+}
+
+// The largest full-piece capacity a workspace of `bytes` holds for S
+// segments, or 0 when it cannot hold the layout of capacity 1.  A workspace
+// of seg_layout(total, S, kMinChunk).bytes holds capacity total / chunk + 1
+// for every chunk >= kMinChunk.
+constexpr int64_t seg_capacity(size_t bytes, int64_t S) {
+  const size_t fixed = seg_layout_cap(1, S).bytes;
+  if (bytes < fixed) return 0;
+  // 8 bytes of list entry + 32 of partial slot per entry; the two rounded
+  // sections differ from that by less than 1024 bytes, so this starts above
+  // the answer and steps down to it.
+  int64_t c = 1 + (int64_t)((bytes - fixed + 1024) / (sizeof(SegPiece) + kPartialBytes));
+  while (c > 1 && seg_layout_cap(c, S).bytes > bytes) --c;
+  return c;
+}
+
+// The largest segment total that `bytes` serves at every chunk length (what
+// the size bucket of a segmented call is taken from).
+constexpr int64_t seg_total_bound(size_t bytes, int64_t S) {
+  const int64_t c = seg_capacity(bytes, S);
+  return c > 0 ? c * kMinChunk - 1 : 0;
 }
 
 
@@ -145,12 +174,15 @@ inline int64_t grid_for(int64_t units, int64_t per_block, int cus, const Tuning&
 
 
 // Chunk length (in 16-byte vectors) of a grouped batch: the tuning's element
-// count, at least one block step and a whole number of block steps.
-inline int64_t batch_chunk_vecs(const Tuning& t, int kvec) {
+// count rounded up to a whole number of block steps, and never fewer than
+// kMinChunk elements, so a call of n elements has at most n / kMinChunk + 1
+// chunks (the bound batch_workspace_bytes is sized for).
+constexpr int64_t batch_chunk_vecs(const Tuning& t, int kvec) {
   const int64_t step = (int64_t)t.block * t.unroll;
+  const int64_t min_vecs = (kMinChunk + kvec - 1) / kvec;
   int64_t v = t.chunk / kvec;
-  if (v < step) v = step;
-  return v / step * step;
+  if (v < min_vecs) v = min_vecs;
+  return (v + step - 1) / step * step;
 }
 
 
@@ -168,11 +200,14 @@ hdc_status run_map_reduce_bf16(const hdc_functor& fm, const hdc_functor& f, cons
                                hdc_accum acc, void* out, void* ws, const Tuning& t, hipStream_t st);
 hdc_status run_map_reduce_i32(const hdc_functor& fm, const hdc_functor& f, const void* x, void* y, int64_t n,
                               hdc_accum acc, void* out, void* ws, const Tuning& t, hipStream_t st);
+// `ws_bytes`: the workspace's size, which sets the work-list capacity.
 hdc_status run_segmented(const hdc_functor& f, hdc_dtype dt, const void* x, const int64_t* off, int64_t nseg,
-                         int64_t total, hdc_accum acc, void* out, void* ws, const Tuning& t, hipStream_t st);
+                         hdc_accum acc, void* out, void* ws, size_t ws_bytes, const Tuning& t, hipStream_t st);
+// `ws_bytes` is the workspace's capacity; a group whose chunk partials do not
+// fit is refused (HDC_ERR_WORKSPACE) before anything is launched.
 hdc_status run_batch(const hdc_functor* fm, const hdc_functor& g, hdc_dtype dt, hdc_accum acc,
-                     const hdc_batch_call* calls, const int32_t* idx, int cnt, void* ws, const Tuning& t,
-                     hipStream_t st);
+                     const hdc_batch_call* calls, const int32_t* idx, int cnt, void* ws, size_t ws_bytes,
+                     const Tuning& t, hipStream_t st);
 
 hdc_status run_scan(const hdc_functor& f, hdc_dtype dt, const void* x, void* y, int64_t n, hdc_accum acc,
                     int exclusive, void* ws, const Tuning& t, hipStream_t st);
@@ -180,9 +215,9 @@ hdc_status run_segmented_scan(const hdc_functor& f, hdc_dtype dt, const void* x,
                               int64_t nseg, void* y, int64_t n, hdc_accum acc, int exclusive, void* ws,
                               const Tuning& t, hipStream_t st);
 // Workspace of a scan (also segmented), for tiles of at least 64 * 16
-// elements: the larger of the three-pass need (tile sums and offsets, at most
-// 16 bytes each per tile) and the single-pass need (256-byte header, then at
-// most 3 words of 8 bytes per tile).
+// elements: a 256-byte header (the status word at byte 4), then the larger
+// of the three-pass need (tile sums and offsets, at most 16 bytes each per
+// tile) and the single-pass need (at most 3 words of 8 bytes per tile).
 constexpr size_t scan_workspace_bytes(int64_t n) {
   const int64_t G = n / 1024 + 1;
   return 256 + 2 * round_up((size_t)G * 24, 256);

@@ -137,12 +137,15 @@ inline hdc_status launch_exact_f16_dot(const void* x, const void* z, int64_t n, 
 }
 
 template <class F, class S, class Acc>
-hdc_status launch_segmented(const F& f, const void* x, const int64_t* off, int64_t nseg, int64_t total, void* out,
-                            void* ws, const Tuning& t, hipStream_t st) {
+hdc_status launch_segmented(const F& f, const void* x, const int64_t* off, int64_t nseg, void* out, void* ws,
+                            size_t ws_bytes, const Tuning& t, hipStream_t st) {
   using T = typename S::T;
   int cus = 0;
   HDC_TRY(compute_units(&cus));
-  const SegLayout l = seg_layout(total, nseg, t.chunk);
+  const int64_t cap = seg_capacity(ws_bytes, nseg);
+  if (cap < 1) return fail(HDC_ERR_WORKSPACE, "workspace of %zu bytes is too small for %lld segments", ws_bytes,
+                           (long long)nseg);
+  const SegLayout l = seg_layout_cap(cap, nseg);
   char* base = static_cast<char*>(ws);
   SegPlan p;
   p.cnt = reinterpret_cast<SegCounters*>(base + l.cnt);
@@ -195,7 +198,7 @@ hdc_status launch_segmented(const F& f, const void* x, const int64_t* off, int64
 
 template <class FM, class F, class S, class Acc>
 hdc_status launch_batch(const FM& fm, const F& f, const hdc_batch_call* calls, const int32_t* idx, int cnt,
-                        void* ws, const Tuning& t, hipStream_t st) {
+                        void* ws, size_t ws_bytes, const Tuning& t, hipStream_t st) {
   int cus = 0;
   HDC_TRY(compute_units(&cus));
   BatchTable tab{};
@@ -216,6 +219,9 @@ hdc_status launch_batch(const FM& fm, const F& f, const hdc_batch_call* calls, c
     }
   }
   tab.prefix[cnt] = acc_chunks;
+  if ((size_t)acc_chunks * sizeof(Acc) > ws_bytes)
+    return fail(HDC_ERR_WORKSPACE, "the batch needs %lld chunk partials (%zu bytes) but the workspace holds %zu bytes",
+                (long long)acc_chunks, (size_t)acc_chunks * sizeof(Acc), ws_bytes);
   Acc* partials = static_cast<Acc*>(ws);
   if (acc_chunks > 0) {
     int64_t g = (int64_t)cus * t.grid_mult;
@@ -239,7 +245,8 @@ hdc_status launch_batch(const FM& fm, const F& f, const hdc_batch_call* calls, c
 // Scan: t.unroll == 1 selects the three-pass schedule, any other value the
 // single pass.  `seg` carries the segment offsets of a segmented scan (Acc a
 // SegAcc), else nothing.  Workspace (scan_workspace_bytes):
-//   three passes: tile sums | tile offsets, one fold state per tile each;
+//   three passes: 256-byte header (status) | tile sums | tile offsets, one
+//                 fold state per tile each;
 //   single pass:  256-byte header (ticket, status) | the tree nodes
 //                 (tree_nodes(G), level by level), kWords 8-byte words each.
 template <class F, class S, class Acc>
@@ -247,6 +254,7 @@ hdc_status launch_scan(const F& f, const void* x, void* y, int64_t n, int exclus
                        const Tuning& t, hipStream_t st) {
   using T = typename S::T;
   using OutT = typename ScanOut<Acc>::T;
+  static_assert(sizeof(Acc) <= 24, "scan_workspace_bytes holds 24 bytes per tile and array");
   const int64_t tile = (int64_t)t.block * kScanE;
   const int64_t G = (n + tile - 1) / tile;
   if (G * t.block > (int64_t)UINT32_MAX) return fail(HDC_ERR_UNSUPPORTED, "n = %lld is too large for one scan", (long long)n);
@@ -271,14 +279,16 @@ hdc_status launch_scan(const F& f, const void* x, void* y, int64_t n, int exclus
       scan_onepass_kernel<F, S, Acc, false, false><<<grid, block, 0, st>>>(f, xp, n, seg, lb, yp, exclusive);
     return check_launch("scan single-pass launch");
   }
-  Acc* sums = static_cast<Acc*>(ws);
-  Acc* offsets = reinterpret_cast<Acc*>(static_cast<char*>(ws) + round_up((size_t)G * sizeof(Acc), 256));
+  // three passes: the same 256-byte header (its status word cleared by the
+  // offsets pass), then the tile sums and the tile offsets
+  Acc* sums = reinterpret_cast<Acc*>(static_cast<char*>(ws) + 256);
+  Acc* offsets = reinterpret_cast<Acc*>(static_cast<char*>(ws) + 256 + round_up((size_t)G * sizeof(Acc), 256));
   if (xa)
     scan_tile_sums_kernel<F, S, Acc, true><<<grid, block, 0, st>>>(f, xp, n, seg, sums);
   else
     scan_tile_sums_kernel<F, S, Acc, false><<<grid, block, 0, st>>>(f, xp, n, seg, sums);
   HDC_TRY(check_launch("scan tile-sum launch"));
-  scan_offsets_kernel<Acc><<<dim3(1), dim3(1024), 0, st>>>(sums, G, offsets);
+  scan_offsets_kernel<Acc><<<dim3(1), dim3(1024), 0, st>>>(sums, G, offsets, static_cast<uint32_t*>(ws) + 1);
   HDC_TRY(check_launch("scan offset launch"));
   if (xa && ya)
     scan_tiles_kernel<F, S, Acc, true, true><<<grid, block, 0, st>>>(f, xp, n, seg, offsets, yp, exclusive);

@@ -466,8 +466,10 @@ __global__ __launch_bounds__(1024) void scan_tile_sums_kernel(F f, const elem_t<
 // a thread folds kScanE consecutive sums (all loaded first), then the block
 // scans the thread totals.
 template <class Acc>
-__global__ __launch_bounds__(1024) void scan_offsets_kernel(const Acc* sums, int64_t G, Acc* offsets) {
+__global__ __launch_bounds__(1024) void scan_offsets_kernel(const Acc* sums, int64_t G, Acc* offsets,
+                                                            uint32_t* status) {
   __shared__ Acc lds[kMaxWaves];
+  if (threadIdx.x == 0) *status = 0;  // this schedule never waits, so it never gives up
   const int lane = threadIdx.x & 63;
   const int64_t R = (int64_t)blockDim.x * kScanE;
   Acc carry = Acc::zero();

@@ -133,6 +133,15 @@ static __global__ __launch_bounds__(kPlanBlock) void seg_write_kernel(const int6
   if (sh.want.part && (int64_t)pre.part < p.cap_part) p.part_list[pre.part] = SegPiece{(int32_t)j, (int32_t)sh.nfull};
 }
 
+// True when the plan's lists exceed the workspace's capacity.  The plan then
+// drops the entries past the end, and the persistent pass instead folds
+// every segment whole with one wavefront (slower; the summation order, and
+// so the last bits of a floating-point result, differ from the planned pass).
+__device__ __forceinline__ bool seg_overflow(const SegPlan& p) {
+  return (int64_t)p.cnt->full > p.cap_full || (int64_t)p.cnt->partials > p.cap_partials ||
+         (int64_t)p.cnt->part > p.cap_part || (int64_t)p.cnt->longs > p.cap_part;
+}
+
 // Final value of a fold state as stored in `out`.
 template <class Acc>
 __device__ __forceinline__ void store_result(void* out, int64_t j, const Acc& a) {
@@ -217,6 +226,15 @@ __global__ __launch_bounds__(1024) void seg_items_kernel(F f, const elem_t<S>* _
   const int64_t w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * wpb + (threadIdx.x >> 6)));
   const int64_t W = (int64_t)gridDim.x * wpb;
   const int64_t cf = p.cnt->full, cp = p.cnt->part;
+  if (seg_overflow(p)) {
+    // The work lists did not fit the workspace (offsets[S] above the total
+    // it was sized for): every segment is folded whole by one wavefront.
+    for (int64_t j = w; j < S_; j += W) {
+      const Acc r = wave_fold_range<F, S, Acc, U>(f, x, off[j], off[j + 1], lane);
+      if (lane == 0) store_result<Acc>(out, j, r);
+    }
+    return;
+  }
   const int64_t nfull = cf < p.cap_full ? cf : p.cap_full;
   const int64_t npart = cp < p.cap_part ? cp : p.cap_part;
   const int64_t npieces = nfull + npart;
@@ -322,6 +340,7 @@ __global__ __launch_bounds__(256) void seg_combine_kernel(const int64_t* __restr
   const int64_t wpb = blockDim.x >> 6;
   const int64_t w = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
   const int64_t W = (int64_t)gridDim.x * wpb;
+  if (seg_overflow(p)) return;  // the persistent pass folded every segment whole
   const int64_t cl = p.cnt->longs;
   const int64_t nlong = cl < p.cap_part ? cl : p.cap_part;
   const Acc* partials = static_cast<const Acc*>(p.partials);

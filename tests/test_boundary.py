@@ -114,12 +114,31 @@ def test_map_reduce_and_segmented_reject_bad_arguments():
     assert L.hdc_map_reduce(ident, fn({"fn": "product"}), hdc.F32, FAKE, FAKE + 4096, 100, 0, FAKE, FAKE, need,
                             None) == hdc.ERR_UNSUPPORTED
     sneed = hdc.workspace_size(hdc.OP_SEGMENTED_REDUCE, hdc.F32, hdc.ACC_PLAIN, 1000, 10)
-    assert L.hdc_segmented_reduce(ident, hdc.F32, FAKE, FAKE, -1, 1000, 0, FAKE, FAKE, sneed, None) \
+    # the section 8(b) signature: (f, dt, x, offsets, S, acc, out, workspace, ws_bytes, stream)
+    assert [a.__name__ for a in L.hdc_segmented_reduce.argtypes[1:]] == [
+        "c_int", "c_void_p", "c_void_p", "c_long", "c_int", "c_void_p", "c_void_p", "c_ulong", "c_void_p"]
+    assert L.hdc_segmented_reduce(ident, hdc.F32, FAKE, FAKE, -1, 0, FAKE, FAKE, sneed, None) \
         == hdc.ERR_INVALID_ARGUMENT
-    assert L.hdc_segmented_reduce(ident, hdc.F32, FAKE, None, 10, 1000, 0, FAKE, FAKE, sneed, None) \
+    assert L.hdc_segmented_reduce(ident, hdc.F32, FAKE, None, 10, 0, FAKE, FAKE, sneed, None) \
         == hdc.ERR_INVALID_ARGUMENT
-    assert L.hdc_segmented_reduce(fn({"fn": "product"}), hdc.F32, FAKE, FAKE, 10, 1000, 0, FAKE, FAKE, sneed,
+    assert L.hdc_segmented_reduce(fn({"fn": "product"}), hdc.F32, FAKE, FAKE, 10, 0, FAKE, FAKE, sneed,
                                   None) == hdc.ERR_UNSUPPORTED
+    assert L.hdc_segmented_reduce(ident, hdc.F32, FAKE, FAKE, 0, 0, FAKE, FAKE, 0, None) == hdc.OK  # S = 0
+    assert L.hdc_segmented_reduce(ident, hdc.F32, FAKE, FAKE, 10, 0, None, FAKE, sneed, None) \
+        == hdc.ERR_INVALID_ARGUMENT  # out NULL
+    assert L.hdc_segmented_reduce(ident, hdc.F32, FAKE, FAKE, 10, 0, FAKE, FAKE + 8, sneed, None) \
+        == hdc.ERR_INVALID_ARGUMENT  # workspace not 256-byte aligned
+    small = hdc.workspace_size(hdc.OP_SEGMENTED_REDUCE, hdc.F32, hdc.ACC_PLAIN, 0, 10)
+    assert L.hdc_segmented_reduce(ident, hdc.F32, FAKE, FAKE, 10, 0, FAKE, FAKE, small - 1, None) \
+        == hdc.ERR_WORKSPACE  # below the bound for 10 segments at any total
+    assert "smaller" in last()
+
+
+def test_scan_status_rejects_bad_arguments():
+    L = hdc.lib()
+    assert L.hdc_scan_status(FAKE, None, None) == hdc.ERR_INVALID_ARGUMENT
+    assert L.hdc_scan_status(FAKE + 8, FAKE, None) == hdc.ERR_INVALID_ARGUMENT
+    assert "256-byte aligned" in last()
 
 
 def test_workspace_sizes():
@@ -191,6 +210,19 @@ def test_scan_tree_shape_and_workspace_bound():
     src = os.path.join(ROOT, "tests", "compile_probes", "scan_tree.hip")
     cmd = ["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-std=c++20", "-fsyntax-only",
            "-fconstexpr-steps=100000000", "-I", os.path.join(ROOT, "include"),
+           "-I", os.path.join(ROOT, "paper_2309_03912_amd", "csrc"), src]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
+def test_batch_and_segmented_workspace_bounds():
+    """Compile-time checks, over every accepted tuning, that a grouped batch's chunks are whole block
+    steps of at least 1024 elements whose partials fit the batch workspace, and that the segmented
+    reduce's work-list capacity read from a workspace size covers the total that size was computed
+    for (tests/compile_probes/workspace_bounds.hip)."""
+    src = os.path.join(ROOT, "tests", "compile_probes", "workspace_bounds.hip")
+    cmd = ["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-std=c++20", "-fsyntax-only",
+           "-fconstexpr-steps=200000000", "-I", os.path.join(ROOT, "include"),
            "-I", os.path.join(ROOT, "paper_2309_03912_amd", "csrc"), src]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr

@@ -74,6 +74,40 @@ def test_map_int_bit_exact(name):
     assert torch.equal(hdc.map(x.to(gpu()), INT_FNS["affine"]).cpu(), oracle.map(INT_FNS["affine"], x))
 
 
+MAP_SHAPES = [(64, 1), (256, 8), (1024, 64)]  # (block, blocks per compute unit)
+
+
+@pytest.mark.parametrize("dt", FLOAT_DTYPES + [torch.int32])
+@pytest.mark.parametrize("unroll", [1, 2, 4, 8])
+def test_map_every_instance_bit_exact(dt, unroll):
+    """Every map kernel instance the tuning can select (16-byte vectors per lane per step 1, 2, 4, 8) at
+    several block and grid shapes, on sizes spanning many grid steps and a ragged tail, from an aligned
+    start and from an unaligned view (peeled head): bit-equal to the oracle."""
+    code = hdc.DTYPE[dt]
+    saved = {b: hdc.get_tuning(hdc.OP_MAP, code, hdc.ACC_PLAIN, b) for b in range(4)}
+    fns = [INT_FNS["affine"]] if dt == torch.int32 else [FNS["affine"], FNS["horner"]]
+    try:
+        for block, gm in MAP_SHAPES:
+            hdc.set_tuning(hdc.OP_MAP, code, hdc.ACC_PLAIN, -1, block=block, unroll=unroll, grid_mult=gm)
+            for n in (70001, (1 << 20) + 13):
+                base = make_x(n + 3, dt, seed=block + unroll + n, scale=3.0)
+                bg = base.to(gpu())
+                yg = torch.empty_like(bg)
+                for lo in (0, 3):
+                    x = base[lo:lo + n]
+                    for fn in fns:
+                        ref = bits(oracle.map(fn, x))
+                        # x and y at the same offset: the vector walk with a peeled head
+                        y = hdc.map(bg[lo:lo + n], fn, out=yg[lo:lo + n])
+                        assert torch.equal(bits(y.cpu()), ref), (block, unroll, gm, n, lo, fn)
+                        if lo:  # different 16-byte offsets: the element-by-element walk
+                            y = hdc.map(bg[lo:lo + n], fn)
+                            assert torch.equal(bits(y.cpu()), ref), (block, unroll, gm, n, lo, fn, "scalar")
+    finally:
+        for b, t in saved.items():
+            hdc.set_tuning(hdc.OP_MAP, code, hdc.ACC_PLAIN, b, **t)
+
+
 @pytest.mark.parametrize("dt", FLOAT_DTYPES + [torch.int32])
 def test_map_misaligned_views_and_in_place(dt):
     n = 100003

@@ -154,3 +154,46 @@ def test_segmented_horner_degrees(degree):
     for acc in ("plain", "compensated"):
         r = hdc.segmented_reduce(x.to(gpu()), off.to(gpu()), fn, acc)
         check_segments(r, oracle.segmented(fn, x, off), f"degree {degree} {acc}")
+
+
+@pytest.mark.parametrize("acc", ["plain", "compensated"])
+def test_segmented_workspace_below_the_total_still_correct(acc):
+    """A workspace sized for a total far below offsets[S]: the work lists cannot hold the pieces, and the
+    persistent pass folds every segment whole instead; every segment still matches the oracle.  Then the
+    same call with the full workspace, whose bits are those of the planned pass."""
+    L = edge_lengths(seed=31, count=500)
+    off = synth.offsets_from_lengths(L)
+    n = int(off[-1])
+    S = L.numel()
+    x = synth.uniform_pm1_f32(31, 0, n)
+    ref = oracle.segmented(FNS["horner"], x, off)
+    g, og = x.to(gpu()), off.to(gpu())
+    small = torch.zeros(hdc.workspace_size(hdc.OP_SEGMENTED_REDUCE, hdc.F32, hdc.ACC[acc], 1000, S),
+                        dtype=torch.uint8, device=gpu())
+    old = hdc.get_tuning(hdc.OP_SEGMENTED_REDUCE, hdc.F32, hdc.ACC[acc], hdc.tuning_bucket(1000))
+    try:  # the bucket of the small workspace: pieces of 1024, so the list overflows for sure
+        hdc.set_tuning(hdc.OP_SEGMENTED_REDUCE, hdc.F32, hdc.ACC[acc], hdc.tuning_bucket(1000), chunk=1024,
+                       small_seg=64)
+        r = hdc.segmented_reduce(g, og, FNS["horner"], acc, ws=small)
+        check_segments(r, ref, f"undersized workspace {acc}")
+    finally:
+        hdc.set_tuning(hdc.OP_SEGMENTED_REDUCE, hdc.F32, hdc.ACC[acc], hdc.tuning_bucket(1000), **old)
+    full = hdc.segmented_reduce(g, og, FNS["horner"], acc)
+    check_segments(full, ref, f"full workspace {acc}")
+
+
+def test_segmented_library_workspace_reads_the_total():
+    """workspace NULL: the library reads offsets[S] from the device to size its own buffer."""
+    import ctypes
+    L = edge_lengths(seed=33, count=300)
+    off = synth.offsets_from_lengths(L)
+    n = int(off[-1])
+    x = synth.uniform_pm1_f32(33, 0, n)
+    g, og = x.to(gpu()), off.to(gpu())
+    out = torch.empty(L.numel(), dtype=torch.float64, device=gpu())
+    f = hdc.make_functor(FNS["horner"])
+    st = hdc.lib().hdc_segmented_reduce(ctypes.byref(f), hdc.F32, g.data_ptr(), og.data_ptr(), L.numel(),
+                                        hdc.ACC_COMPENSATED, out.data_ptr(), None, 0,
+                                        torch.cuda.current_stream().cuda_stream)
+    assert st == hdc.OK, hdc.lib().hdc_last_error()
+    check_segments(out, oracle.segmented(FNS["horner"], x, off), "library workspace")

@@ -114,10 +114,8 @@ def test_segscan_single_segment_equals_scan_and_deterministic(schedule):
     off2 = synth.offsets_from_lengths(L)
     m = int(off2[-1])
     x2 = synth.uniform_pm1_f32(15, 0, m)
-    y = hdc.segmented_scan(x2.to(gpu()), off2.to(gpu()), HOR, "plain", ws=ws)
-    if schedule == "single_pass":
-        torch.cuda.synchronize()
-        assert int(ws[4:8].cpu().view(torch.int32).item()) == 0
+    y = hdc.segmented_scan(x2.to(gpu()), off2.to(gpu()), HOR, "plain", ws=ws, check=False)
+    assert hdc.scan_status(ws) == 0
     check_float(y, oracle.segmented_scan(HOR, x2, off2), inside(off2, m), "many segments")
 
 
@@ -128,7 +126,9 @@ def test_segscan_lognormal_full_size_sampled():
     off = synth.offsets_from_lengths(L)
     n = int(off[-1])
     xg = synth.uniform_pm1_f32(seed, synth.STREAM["x"], n, gpu())
-    y = hdc.segmented_scan(xg, off.to(gpu()), HOR, "plain").cpu()
+    ws = hdc.workspace(gpu(), hdc.OP_SCAN, hdc.F32, hdc.ACC_PLAIN, n)
+    y = hdc.segmented_scan(xg, off.to(gpu()), HOR, "plain", ws=ws, check=False).cpu()
+    assert hdc.scan_status(ws) == 0
     xc = xg.cpu()
     rng = np.random.default_rng(5)
     segs = rng.integers(0, L.numel(), 300)
@@ -159,10 +159,14 @@ def test_segscan_many_small_tiles(schedule):
         assert (n + 1023) // 1024 == 4101
         mask = inside(off, n)
         x = synth.uniform_pm1_f32(14, 0, n)
-        y = hdc.segmented_scan(x.to(gpu()), off.to(gpu()), HOR, "compensated")
+        ws = hdc.workspace(gpu(), hdc.OP_SCAN, hdc.F32, hdc.ACC_COMPENSATED, n)
+        y = hdc.segmented_scan(x.to(gpu()), off.to(gpu()), HOR, "compensated", ws=ws, check=False)
+        assert hdc.scan_status(ws) == 0
         check_float(y, oracle.segmented_scan(HOR, x, off), mask, "f32 compensated, block 64")
         xi = synth.uniform_int(15, 10, n)
-        yi = hdc.segmented_scan(xi.to(gpu()), off.to(gpu()), IAFF, "exact_int", exclusive=True)
+        yi = hdc.segmented_scan(xi.to(gpu()), off.to(gpu()), IAFF, "exact_int", exclusive=True, ws=ws,
+                                check=False)
+        assert hdc.scan_status(ws) == 0
         ref = oracle.segmented_scan(IAFF, xi, off, True)["isum"]
         assert np.array_equal(yi.cpu().numpy()[mask], ref[mask])
     finally:
