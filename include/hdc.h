@@ -158,6 +158,31 @@ hdc_status hdc_transform_reduce(const hdc_functor* f, hdc_dtype dt,
                                 size_t ws_bytes, void* stream);
 
 /*
+ * hdc_transform_reduce without a workspace and without any allocation, for
+ * callers that cannot allocate device memory: code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.
+ *   Arguments, results and errors are those of hdc_transform_reduce (the same
+ *   kernels, tuning and summation order, so the same bits), minus workspace
+ *   and ws_bytes: the per-block partials go to a scratch array of 2 MiB
+ *   compiled into the library, one copy per device, held from the first
+ *   call on that device until the process ends.  The scratch holds the
+ *   partials of the most blocks any call launches, so every n that
+ *   hdc_transform_reduce accepts fits; a call that needed more would fail
+ *   with HDC_ERR_WORKSPACE before enqueuing anything.  The call never runs
+ *   hipMalloc, hipFree or an allocating library routine; the first call on
+ *   a device looks up the scratch array's device address (no allocation).
+ *   Every call on one device shares that device's scratch: calls that may
+ *   overlap in time on one device (different streams, or graphs replayed
+ *   concurrently) race and give wrong results.  Order them on one stream.
+ *   The scratch keeps the last call's partials; nothing in it needs to start
+ *   at zero (each call writes every partial it reads).
+ */
+hdc_status hdc_transform_reduce_noalloc(const hdc_functor* f, hdc_dtype dt,
+                                        const void* x, const void* z,
+                                        int64_t n, hdc_accum acc, void* out,
+                                        void* stream);
+
+/*
  * out[j] = sum_{offsets[j] <= i < offsets[j+1]} f(x[i]) for 0 <= j < S.
  *   The per-element callable as in hdc_transform_reduce (section 2.4,
  *   listing lst_solution_ifdef_cudaarch), folded separately over each of

@@ -40,8 +40,8 @@ FN = {"identity": FN_IDENTITY, "affine": FN_AFFINE, "horner": FN_HORNER, "produc
 
 # Every symbol include/hdc.h declares.
 EXPORTS = [
-    "hdc_map", "hdc_transform_reduce", "hdc_segmented_reduce", "hdc_map_reduce", "hdc_batch_map_reduce",
-    "hdc_host_map", "hdc_host_transform_reduce", "hdc_scan", "hdc_segmented_scan", "hdc_scan_status",
+    "hdc_map", "hdc_transform_reduce", "hdc_transform_reduce_noalloc", "hdc_segmented_reduce", "hdc_map_reduce",
+    "hdc_batch_map_reduce", "hdc_host_map", "hdc_host_transform_reduce", "hdc_scan", "hdc_segmented_scan", "hdc_scan_status",
     "hdc_workspace_size", "hdc_validate_offsets", "hdc_set_tuning", "hdc_get_tuning",
     "hdc_load_tuning", "hdc_tuning_bucket", "hdc_status_string", "hdc_last_error", "hdc_version",
 ]
@@ -88,6 +88,7 @@ def lib() -> ctypes.CDLL:
         st = ctypes.c_int
         L.hdc_map.argtypes = [P(Functor), i32, vp, vp, i64, vp]
         L.hdc_transform_reduce.argtypes = [P(Functor), i32, vp, vp, i64, i32, vp, vp, ctypes.c_size_t, vp]
+        L.hdc_transform_reduce_noalloc.argtypes = [P(Functor), i32, vp, vp, i64, i32, vp, vp]
         L.hdc_segmented_reduce.argtypes = [P(Functor), i32, vp, vp, i64, i32, vp, vp, ctypes.c_size_t, vp]
         L.hdc_map_reduce.argtypes = [P(Functor), P(Functor), i32, vp, vp, i64, i32, vp, vp, ctypes.c_size_t, vp]
         L.hdc_batch_map_reduce.argtypes = [P(Functor), P(Functor), i32, i32, P(BatchCall), ctypes.c_int32, vp,
@@ -104,8 +105,8 @@ def lib() -> ctypes.CDLL:
         L.hdc_get_tuning.argtypes = [i32, i32, i32, i32, P(Tuning)]
         L.hdc_tuning_bucket.argtypes = [i64, P(ctypes.c_int32)]
         L.hdc_load_tuning.argtypes = [ctypes.c_char_p]
-        for name in ["hdc_map", "hdc_transform_reduce", "hdc_segmented_reduce", "hdc_map_reduce",
-                     "hdc_batch_map_reduce", "hdc_host_map", "hdc_host_transform_reduce", "hdc_scan",
+        for name in ["hdc_map", "hdc_transform_reduce", "hdc_transform_reduce_noalloc", "hdc_segmented_reduce",
+                     "hdc_map_reduce", "hdc_batch_map_reduce", "hdc_host_map", "hdc_host_transform_reduce", "hdc_scan",
                      "hdc_segmented_scan", "hdc_scan_status", "hdc_workspace_size", "hdc_validate_offsets",
                      "hdc_set_tuning", "hdc_get_tuning", "hdc_load_tuning", "hdc_tuning_bucket"]:
             getattr(L, name).restype = st
@@ -248,6 +249,26 @@ def transform_reduce(x: torch.Tensor, fn, acc="plain", z: torch.Tensor | None = 
     f = make_functor(fn)
     _check(lib().hdc_transform_reduce(ctypes.byref(f), dt, x.data_ptr(), zp, x.numel(), a, r.data_ptr(),
                                       ws.data_ptr(), ws.numel(), _stream(x)))
+    return r
+
+
+def transform_reduce_noalloc(x: torch.Tensor, fn, acc="plain", z: torch.Tensor | None = None,
+                             out: torch.Tensor | None = None) -> torch.Tensor:
+    """transform_reduce through hdc_transform_reduce_noalloc: no workspace, the partials go to
+    the library's per-device scratch array.  Pass ``out`` to keep the call free of allocations."""
+    x = _gpu_tensor(x, "x")
+    a = _acc(acc)
+    dt = _dtype(x)
+    zp = None
+    if z is not None:
+        z = _gpu_tensor(z, "z")
+        if z.dtype != x.dtype or z.numel() != x.numel():
+            raise ValueError("z must match x in dtype and size")
+        zp = z.data_ptr()
+    r = torch.empty((), dtype=OUT_DTYPE[a], device=x.device) if out is None else out
+    f = make_functor(fn)
+    _check(lib().hdc_transform_reduce_noalloc(ctypes.byref(f), dt, x.data_ptr(), zp, x.numel(), a, r.data_ptr(),
+                                              _stream(x)))
     return r
 
 

@@ -201,6 +201,40 @@ hdc_status resolve_workspace(void* ws, size_t ws_bytes, size_t need, hipStream_t
 }
 
 // ---------------------------------------------------------------------------
+// Scratch of the allocation-free transform_reduce
+// ---------------------------------------------------------------------------
+
+// The pass-1 partials of hdc_transform_reduce_noalloc: one 32-byte fold
+// state per block, for the most blocks any call launches (kMaxGrid).  Each
+// device holds its own copy from module load until the process ends.  In
+// host code `scratch` names a host-side shadow, never the device memory:
+// the kernels get the device address that hipGetSymbolAddress returns.
+constexpr size_t kScratchBytes = size_t(2) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];  // device address of `scratch` per device, null until set up
+
+// The device address of the current device's `scratch`, looked up once per
+// device with that device current.
+hdc_status scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(HDC_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(HDC_ERR_HIP, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(HDC_ERR_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return HDC_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Argument checks
 // ---------------------------------------------------------------------------
 
@@ -278,9 +312,11 @@ hdc_status hdc_map(const hdc_functor* f, hdc_dtype dt, const void* x, void* y, i
   return run_map(*f, dt, x, y, n, t, st);
 }
 
+// `noalloc`: the partials go to the library's scratch array (workspace and
+// ws_bytes are ignored).
 static hdc_status reduce_common(const hdc_functor* f, const hdc_functor* fm, hdc_dtype dt, const void* x,
                                 const void* z, void* y, int64_t n, hdc_accum acc, void* out, void* workspace,
-                                size_t ws_bytes, void* stream) {
+                                size_t ws_bytes, void* stream, bool noalloc = false) {
   const bool fused = fm != nullptr;
   HDC_TRY(check_functor(f, dt, !fused));
   if (fused) HDC_TRY(check_functor(fm, dt, false));
@@ -307,7 +343,14 @@ static hdc_status reduce_common(const hdc_functor* f, const hdc_functor* fm, hdc
   if (!out) return fail(HDC_ERR_INVALID_ARGUMENT, "out is NULL");
   hipStream_t st = (hipStream_t)stream;
   void* ws = nullptr;
-  HDC_TRY(resolve_workspace(workspace, ws_bytes, reduce_workspace_bytes(), st, &ws));
+  if (noalloc) {
+    if (reduce_workspace_bytes() > kScratchBytes)
+      return fail(HDC_ERR_WORKSPACE, "the call needs %zu bytes of partials; the scratch array holds %zu",
+                  reduce_workspace_bytes(), kScratchBytes);
+    HDC_TRY(scratch_address(&ws));
+  } else {
+    HDC_TRY(resolve_workspace(workspace, ws_bytes, reduce_workspace_bytes(), st, &ws));
+  }
   const int op = fused ? HDC_OP_MAP_REDUCE : f->id == HDC_FN_PRODUCT ? HDC_OP_DOT : HDC_OP_TRANSFORM_REDUCE;
   const Tuning t = tuning_for(op, dt, acc, n);
 
@@ -324,6 +367,11 @@ static hdc_status reduce_common(const hdc_functor* f, const hdc_functor* fm, hdc
 hdc_status hdc_transform_reduce(const hdc_functor* f, hdc_dtype dt, const void* x, const void* z, int64_t n,
                                 hdc_accum acc, void* out, void* workspace, size_t ws_bytes, void* stream) {
   return reduce_common(f, nullptr, dt, x, z, nullptr, n, acc, out, workspace, ws_bytes, stream);
+}
+
+hdc_status hdc_transform_reduce_noalloc(const hdc_functor* f, hdc_dtype dt, const void* x, const void* z,
+                                        int64_t n, hdc_accum acc, void* out, void* stream) {
+  return reduce_common(f, nullptr, dt, x, z, nullptr, n, acc, out, nullptr, 0, stream, true);
 }
 
 hdc_status hdc_map_reduce(const hdc_functor* f, const hdc_functor* g, hdc_dtype dt, const void* x, void* y,

@@ -103,6 +103,21 @@ def test_transform_reduce_rejects_bad_arguments():
     assert "256-byte aligned" in last()
 
 
+def test_transform_reduce_noalloc_rejects_bad_arguments():
+    L = hdc.lib()
+    ident = fn({"fn": "identity"})
+    args = lambda **k: (k.get("f", ident), k.get("dt", hdc.F32), k.get("x", FAKE), k.get("z", None),
+                        k.get("n", 100), k.get("acc", hdc.ACC_PLAIN), k.get("out", FAKE), None)
+    assert L.hdc_transform_reduce_noalloc(*args(f=None)) == hdc.ERR_INVALID_ARGUMENT
+    assert L.hdc_transform_reduce_noalloc(*args(n=-5)) == hdc.ERR_INVALID_ARGUMENT
+    assert L.hdc_transform_reduce_noalloc(*args(x=None)) == hdc.ERR_INVALID_ARGUMENT
+    assert L.hdc_transform_reduce_noalloc(*args(x=FAKE + 2)) == hdc.ERR_INVALID_ARGUMENT
+    assert L.hdc_transform_reduce_noalloc(*args(out=None)) == hdc.ERR_INVALID_ARGUMENT
+    assert L.hdc_transform_reduce_noalloc(*args(acc=hdc.ACC_EXACT_INT)) == hdc.ERR_UNSUPPORTED
+    assert L.hdc_transform_reduce_noalloc(*args(f=fn({"fn": "product"}))) == hdc.ERR_UNSUPPORTED  # no z
+    assert L.hdc_transform_reduce_noalloc(*args(acc=hdc.ACC_EXACT)) == hdc.ERR_UNSUPPORTED
+
+
 def test_map_reduce_and_segmented_reject_bad_arguments():
     L = hdc.lib()
     ident = fn({"fn": "identity"})
