@@ -349,7 +349,17 @@ hdc_status hdc_validate_offsets(const int64_t* offsets, int64_t num_segments,
  * how many small segments share one wavefront (power of two, 1..64, each
  * served by 64/seg_per_wave lanes).  For HDC_OP_SCAN, block sets the tile
  * (block * 16 elements) and unroll 1 selects the three-pass schedule.
- * Tuning changes
+ * passes, 1 or 2 (default 2).  HDC_OP_TRANSFORM_REDUCE, HDC_OP_DOT,
+ * HDC_OP_MAP_REDUCE: 1 folds the per-block partials in the same launch, in
+ * the block that arrives last on a ticket (library-owned device memory, one
+ * per workspace buffer), if the grid's partials fit its LDS stage (32 KiB),
+ * else in a second launch; 2 always folds them in a second launch.  Both
+ * fold in the same order, so `passes` does not change any result bit.  (A
+ * one-launch fold whose wait for a partial gave up -- not expected -- writes
+ * NaN, or INT64_MIN for int64 sums.)  The exact bf16 sum and the exact fp16
+ * dot always use two launches.  HDC_OP_SEGMENTED_REDUCE: 1 selects the tiled
+ * schedule (fixed tiles of `chunk` elements, no plan), 2 the planned one
+ * (pieces of `chunk`, packed small segments).  Tuning changes
  * the summation order, so the last bits of a floating-point sum may change;
  * results stay within the stated tolerance. */
 typedef struct hdc_tuning {
@@ -359,6 +369,7 @@ typedef struct hdc_tuning {
   int32_t chunk;
   int32_t small_seg;
   int32_t seg_per_wave;
+  int32_t passes;
 } hdc_tuning;
 
 /* Set the class (bucket -1: every bucket); fields set to 0 keep their value.
@@ -370,8 +381,8 @@ hdc_status hdc_get_tuning(int op, hdc_dtype dt, hdc_accum acc, int bucket,
 /* The size bucket a call of n elements falls in. */
 hdc_status hdc_tuning_bucket(int64_t n, int32_t* bucket);
 /* Load a tuning cache written by the autotuner: one line per class,
- * "op dtype acc bucket block unroll grid_mult chunk small_seg seg_per_wave",
- * '#' starts a
+ * "op dtype acc bucket block unroll grid_mult chunk small_seg seg_per_wave
+ * [passes]" (passes may be left out: 2), '#' starts a
  * comment line.  NULL reads the path in the HDC_TUNE_CACHE environment
  * variable (which is also read once, before the first call).  A missing file
  * is not an error; a malformed line is reported and skipped. */

@@ -44,12 +44,17 @@ class OrResult(ctypes.Structure):
                 ("abs_sum", ctypes.c_double), ("isum", ctypes.c_int64)]
 
 
+MT_LIB_PATH = os.path.join(HERE, "liboracle_mt.so")
+
+
 def build() -> str:
-    """Compile liboracle.so with gcc (always recompiles)."""
-    src = os.path.join(HERE, "oracle.c")
-    tmp = LIB_PATH + ".tmp"
-    subprocess.run(["gcc", *CFLAGS, "-o", tmp, src, "-lm"], check=True)
-    os.replace(tmp, LIB_PATH)
+    """Compile liboracle.so and liboracle_mt.so (the same oracle on several host
+    threads, for the multicore CPU baseline) with gcc (always recompiles)."""
+    for src, out, extra in ((os.path.join(HERE, "oracle.c"), LIB_PATH, []),
+                            (os.path.join(HERE, "oracle_mt.c"), MT_LIB_PATH, ["-lpthread"])):
+        tmp = out + ".tmp"
+        subprocess.run(["gcc", *CFLAGS, "-o", tmp, src, "-lm", *extra], check=True)
+        os.replace(tmp, out)
     return LIB_PATH
 
 
@@ -90,6 +95,34 @@ def lib():
         L.or_exact_sum.argtypes = [ctypes.c_void_p, ctypes.c_int64]
         _lib = L
     return _lib
+
+
+_mt_lib = None
+
+
+def mt_lib():
+    global _mt_lib
+    if _mt_lib is None:
+        if not os.path.exists(MT_LIB_PATH):
+            build()
+        L = ctypes.CDLL(MT_LIB_PATH)
+        P = ctypes.POINTER
+        L.or_reduce_mt.restype = ctypes.c_int
+        L.or_reduce_mt.argtypes = [P(OrFn), ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                   ctypes.c_int, P(OrResult)]
+        L.or_map_mt.restype = ctypes.c_int
+        L.or_map_mt.argtypes = [P(OrFn), ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                ctypes.c_int]
+        _mt_lib = L
+    return _mt_lib
+
+
+def host_threads() -> int:
+    """Host cores this process may run on."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
 
 
 def make_fn(spec: dict) -> OrFn:
@@ -138,6 +171,34 @@ def reduce(spec: dict, x: torch.Tensor, z: torch.Tensor | None = None) -> dict:
     r = OrResult()
     if lib().or_reduce(ctypes.byref(f), DTYPES[x.dtype], x.data_ptr(), zp, x.numel(),
                        ctypes.byref(r)) != 0:
+        raise ValueError("oracle: unsupported reduce")
+    return {"exact": r.exact, "seq64": r.seq64, "abs_sum": r.abs_sum, "isum": r.isum}
+
+
+def map_mt(spec: dict, x: torch.Tensor, threads: int | None = None) -> torch.Tensor:
+    """map() on `threads` host threads (default: every core of the affinity mask)."""
+    x = _host(x)
+    y = torch.empty_like(x)
+    f = make_fn(spec)
+    if mt_lib().or_map_mt(ctypes.byref(f), DTYPES[x.dtype], x.data_ptr(), y.data_ptr(), x.numel(),
+                          threads or host_threads()) != 0:
+        raise ValueError("oracle: unsupported map")
+    return y
+
+
+def reduce_mt(spec: dict, x: torch.Tensor, z: torch.Tensor | None = None, threads: int | None = None) -> dict:
+    """reduce() on `threads` host threads: the same exact and integer results; seq64 is the
+    in-order sum of the per-thread fp64 sums."""
+    x = _host(x)
+    zp = None
+    if z is not None:
+        z = _host(z)
+        assert z.dtype == x.dtype and z.numel() == x.numel()
+        zp = z.data_ptr()
+    f = make_fn(spec)
+    r = OrResult()
+    if mt_lib().or_reduce_mt(ctypes.byref(f), DTYPES[x.dtype], x.data_ptr(), zp, x.numel(),
+                             threads or host_threads(), ctypes.byref(r)) != 0:
         raise ValueError("oracle: unsupported reduce")
     return {"exact": r.exact, "seq64": r.seq64, "abs_sum": r.abs_sum, "isum": r.isum}
 

@@ -269,27 +269,24 @@ double or_exact_sum(const double *v, int64_t n) {
 /* Reductions                                                                */
 /* ------------------------------------------------------------------------ */
 
-static void reduce_range(const or_fn *f, int dtype, const void *x,
-                         const void *z, int64_t lo, int64_t hi, or_result *r) {
+/* The fold of the terms of [lo, hi) into caller-held accumulators (an exact
+ * accumulator, the fp64 sum of f in fp64, the fp64 sum of |terms|, the
+ * wrapping integer sum), so that the folds of consecutive ranges can be
+ * joined without rounding. */
+static void fold_range(const or_fn *f, int dtype, const void *x, const void *z,
+                       int64_t lo, int64_t hi, sacc *s, double *seq,
+                       double *abs_sum, uint64_t *isum) {
   if (dtype == OR_I32) {
-    uint64_t acc = 0;
-    double abs_sum = 0.0;
     for (int64_t i = lo; i < hi; ++i) {
       int64_t v = ((const int32_t *)x)[i];
       uint64_t t = f->kind == OR_AFFINE
                        ? (uint64_t)f->ia * (uint64_t)v + (uint64_t)f->ib
                        : (uint64_t)v;
-      acc += t;                                      /* wraps mod 2^64 */
-      abs_sum += fabs((double)(int64_t)t);
+      *isum += t;                                    /* wraps mod 2^64 */
+      *abs_sum += fabs((double)(int64_t)t);
     }
-    r->isum = (int64_t)acc;
-    r->exact = r->seq64 = (double)(int64_t)acc;
-    r->abs_sum = abs_sum;
     return;
   }
-  sacc s;
-  sa_init(&s);
-  double seq = 0.0, abs_sum = 0.0;
   for (int64_t i = lo; i < hi; ++i) {
     double xi = widen(dtype, x, i), t, t64;
     if (f->kind == OR_PRODUCT) {
@@ -299,14 +296,28 @@ static void reduce_range(const or_fn *f, int dtype, const void *x,
       t = (double)or_term_f32(f, (float)xi);
       t64 = or_term_f64(f, xi);
     }
-    sa_add(&s, t);
-    seq += t64;
-    abs_sum += fabs(t);
+    sa_add(s, t);
+    *seq += t64;
+    *abs_sum += fabs(t);
   }
-  r->exact = sa_round(&s);
-  r->seq64 = seq;
+}
+
+static void reduce_range(const or_fn *f, int dtype, const void *x,
+                         const void *z, int64_t lo, int64_t hi, or_result *r) {
+  sacc s;
+  sa_init(&s);
+  double seq = 0.0, abs_sum = 0.0;
+  uint64_t isum = 0;
+  fold_range(f, dtype, x, z, lo, hi, &s, &seq, &abs_sum, &isum);
+  if (dtype == OR_I32) {
+    r->isum = (int64_t)isum;
+    r->exact = r->seq64 = (double)(int64_t)isum;
+  } else {
+    r->exact = sa_round(&s);
+    r->seq64 = seq;
+    r->isum = 0;
+  }
   r->abs_sum = abs_sum;
-  r->isum = 0;
 }
 
 int or_reduce(const or_fn *f, int dtype, const void *x, const void *z,

@@ -57,7 +57,8 @@ class Functor(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("unroll", ctypes.c_int32),
                 ("grid_mult", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("small_seg", ctypes.c_int32), ("seg_per_wave", ctypes.c_int32)]
+                ("small_seg", ctypes.c_int32), ("seg_per_wave", ctypes.c_int32),
+                ("passes", ctypes.c_int32)]
 
 
 class BatchCall(ctypes.Structure):
@@ -449,9 +450,9 @@ def tuning_bucket(n: int) -> int:
 
 
 def set_tuning(op: int, dtype: int, acc: int, bucket: int = -1, block=0, unroll=0, grid_mult=0, chunk=0,
-               small_seg=0, seg_per_wave=0) -> None:
+               small_seg=0, seg_per_wave=0, passes=0) -> None:
     """Set a tuning class; bucket -1 sets every size bucket; 0 keeps a field."""
-    t = Tuning(block, unroll, grid_mult, chunk, small_seg, seg_per_wave)
+    t = Tuning(block, unroll, grid_mult, chunk, small_seg, seg_per_wave, passes)
     _check(lib().hdc_set_tuning(op, dtype, acc, bucket, ctypes.byref(t)))
 
 
@@ -459,7 +460,7 @@ def get_tuning(op: int, dtype: int, acc: int, bucket: int = 3) -> dict:
     t = Tuning()
     _check(lib().hdc_get_tuning(op, dtype, acc, bucket, ctypes.byref(t)))
     return {"block": t.block, "unroll": t.unroll, "grid_mult": t.grid_mult, "chunk": t.chunk,
-            "small_seg": t.small_seg, "seg_per_wave": t.seg_per_wave}
+            "small_seg": t.small_seg, "seg_per_wave": t.seg_per_wave, "passes": t.passes}
 
 
 def load_tuning(path: str | None = None) -> None:

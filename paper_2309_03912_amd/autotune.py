@@ -1,8 +1,9 @@
 """Autotuner of the library's launch parameters.
 
 For each tuning class (op, dtype, accumulation, size bucket) it times every
-candidate setting of (block, unroll, grid_mult) -- and, for the segmented op,
-(chunk, small_seg, seg_per_wave) -- on a synthetic workload of that class:
+candidate setting of (block, unroll, grid_mult) -- then, for the segmented op,
+(chunk, small_seg, seg_per_wave), and for the reductions one or two launches
+(passes) -- on a synthetic workload of that class:
 
   * HIP events on the launching stream, `reps` calls per measurement, median
     of `rounds` measurements; candidates are interleaved round by round so
@@ -14,7 +15,7 @@ candidate setting of (block, unroll, grid_mult) -- and, for the segmented op,
     so that is 1e-6 of the result).
 
 The winners are written as a tuning cache (one line per class:
-"op dtype acc bucket block unroll grid_mult chunk small_seg seg_per_wave"),
+"op dtype acc bucket block unroll grid_mult chunk small_seg seg_per_wave passes"),
 which the library reads through hdc_load_tuning / HDC_TUNE_CACHE.
 
     python -m paper_2309_03912_amd.autotune --out paper_2309_03912_amd/tuning_gfx950.txt
@@ -40,7 +41,7 @@ from . import batch_map_reduce, map_reduce, scan, scan_status, segmented_reduce,
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(HERE, "tuning_gfx950.txt")
 TORCH_DT = {F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16, I32: torch.int32}
-FIELDS = ["block", "unroll", "grid_mult", "chunk", "small_seg", "seg_per_wave"]
+FIELDS = ["block", "unroll", "grid_mult", "chunk", "small_seg", "seg_per_wave", "passes"]
 
 
 def _inputs(dt, n, dev, seed=1):
@@ -176,22 +177,33 @@ def candidates(op, quick=False):
         return base, [dict(chunk=c) for c in [8192, 16384, 32768, 65536]]
     if op == OP_SCAN:  # tile size x schedule (unroll 1: three passes, else one pass)
         return [dict(block=b, unroll=u) for b in [256, 512, 1024] for u in [1, 4]]
+    if op in (OP_TRANSFORM_REDUCE, OP_DOT, OP_MAP_REDUCE):  # geometry, then one or two launches
+        return base, [dict(passes=p) for p in (1, 2)]
     if op != OP_SEGMENTED_REDUCE:
         return base
     seg = [dict(chunk=c, small_seg=s, seg_per_wave=w)
            for c, s, w in itertools.product([2048, 4096, 8192] if quick else [1024, 2048, 4096, 8192, 16384],
                                             [64, 128, 256, 512], [2, 4, 8, 16] if quick else [1, 2, 4, 8, 16, 32, 64])]
-    # two stages: geometry at the default segment split, then the split at the best geometry
-    return base, seg
+    # three stages: the schedule (tiled or planned), the geometry at the default split, then the split
+    # (tile length for the tiled schedule; piece length and small-segment packing for the planned one)
+    return [dict(passes=p) for p in (1, 2)], base, seg
 
 
 def tune_case(case: Case, quick=False, reps=5, rounds=3, log=print):
     op, dt, acc, b = case.key()
     cands = candidates(op, quick)
-    stages = list(cands) if op in (OP_SEGMENTED_REDUCE, OP_BATCH) else [cands]
+    stages = list(cands) if isinstance(cands, tuple) else [cands]
     best = get_tuning(op, dt, acc, b)
     for stage in stages:
         trial = [dict(best, **c) for c in stage]
+        if op == OP_SEGMENTED_REDUCE and best.get("passes") == 1:  # tiled: only the tile length matters
+            seen, uniq = set(), []
+            for c in trial:
+                key = tuple(sorted((k, v) for k, v in c.items() if k not in ("small_seg", "seg_per_wave")))
+                if key not in seen:
+                    seen.add(key)
+                    uniq.append(c)
+            trial = uniq
         times = {i: [] for i in range(len(trial))}
         ref = None
         for r in range(rounds):
@@ -259,7 +271,8 @@ def default_cases(dev, quick=False, log2n=28):
 
 
 def write_cache(path, results):
-    lines = ["# hdc tuning cache (gfx950): op dtype acc bucket block unroll grid_mult chunk small_seg seg_per_wave"]
+    lines = ["# hdc tuning cache (gfx950): op dtype acc bucket block unroll grid_mult chunk small_seg seg_per_wave "
+             "passes"]
     for (op, dt, acc, b), t in sorted(results.items()):
         lines.append(" ".join(str(v) for v in (op, dt, acc, b, *(t[f] for f in FIELDS))))
     with open(path, "w") as f:
@@ -274,7 +287,7 @@ def read_cache(path):
             if line.startswith("#") or not line.strip():
                 continue
             v = [int(w) for w in line.split()]
-            results[tuple(v[:4])] = dict(zip(FIELDS, v[4:]))
+            results[tuple(v[:4])] = dict(zip(FIELDS, v[4:] + [2] * (len(FIELDS) + 4 - len(v))))
     return results
 
 

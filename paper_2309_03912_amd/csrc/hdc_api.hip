@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <unordered_map>
 #include <mutex>
 #include <string>
 #include <utility>
@@ -98,7 +99,7 @@ bool valid_tuning(const Tuning& t) {
   return t.block >= 64 && t.block <= 1024 && t.block % 64 == 0 &&
          (t.unroll == 1 || t.unroll == 2 || t.unroll == 4 || t.unroll == 8) && t.grid_mult >= 1 &&
          t.grid_mult <= 64 && pow2(t.chunk) && t.chunk >= 1024 && t.chunk <= 65536 && t.small_seg >= 0 &&
-         t.small_seg <= 1024 && pow2(t.seg_per_wave) && t.seg_per_wave <= 64;
+         t.small_seg <= 1024 && pow2(t.seg_per_wave) && t.seg_per_wave <= 64 && (t.passes == 1 || t.passes == 2);
 }
 
 hdc_status load_tuning_file(const char* path) {
@@ -111,10 +112,10 @@ hdc_status load_tuning_file(const char* path) {
     ++lineno;
     if (line[0] == '#' || line[0] == '\n') continue;
     int op, dt, acc, bucket;
-    Tuning t;
-    if (sscanf(line, "%d %d %d %d %d %d %d %d %d %d", &op, &dt, &acc, &bucket, &t.block, &t.unroll,
-               &t.grid_mult, &t.chunk, &t.small_seg, &t.seg_per_wave) != 10 ||
-        !valid_class(op, dt, acc, bucket) || bucket < 0 || !valid_tuning(t)) {
+    Tuning t;  // a line without the last field (passes) keeps its default
+    const int got = sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d", &op, &dt, &acc, &bucket, &t.block, &t.unroll,
+                           &t.grid_mult, &t.chunk, &t.small_seg, &t.seg_per_wave, &t.passes);
+    if ((got != 10 && got != 11) || !valid_class(op, dt, acc, bucket) || bucket < 0 || !valid_tuning(t)) {
       st = fail(HDC_ERR_INVALID_ARGUMENT, "tuning cache %s: bad line %d", path, lineno);
       continue;
     }
@@ -231,6 +232,54 @@ hdc_status scratch_address(void** out) {
     g_scratch_ptr[dev] = p;
   }
   *out = g_scratch_ptr[dev];
+  return HDC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Tickets of the one-launch reductions
+// ---------------------------------------------------------------------------
+
+// A one-launch reduction counts its finished blocks on a ticket (a launch
+// epoch and an arrival count) whose count must be 0 when the kernel starts;
+// the block that arrives last folds the partials and moves the ticket to the
+// next epoch with a count of 0.  The tickets are library-owned device memory
+// (an object of static storage, so zero-initialized when the code object is
+// loaded), one per workspace buffer: calls that share a workspace are ordered
+// on one stream, so they never use one ticket at the same time, while calls
+// on different workspaces never share one.  Once every slot of a device is
+// taken, calls with new workspace buffers use the two-launch form.
+constexpr int kTicketSlots = 1 << 16;
+static __device__ uint64_t tickets[kTicketSlots];
+
+struct TicketTable {
+  uint64_t* base = nullptr;  // device address of `tickets` on this device
+  std::unordered_map<const void*, int> slot;
+};
+std::mutex g_ticket_mu;
+TicketTable g_ticket_tables[kMaxDevices];
+
+// The ticket of workspace buffer `ws` on the current device, or NULL when
+// no slot is left.
+hdc_status ticket_for(const void* ws, uint64_t** out) {
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(HDC_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(HDC_ERR_HIP, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> g(g_ticket_mu);
+  TicketTable& tt = g_ticket_tables[dev];
+  if (!tt.base) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(tickets));
+    if (e != hipSuccess || !p) return fail(HDC_ERR_HIP, "hipGetSymbolAddress(tickets): %s", hipGetErrorString(e));
+    tt.base = static_cast<uint64_t*>(p);
+  }
+  auto it = tt.slot.find(ws);
+  if (it == tt.slot.end()) {
+    if (tt.slot.size() >= (size_t)kTicketSlots) return HDC_OK;
+    it = tt.slot.emplace(ws, (int)tt.slot.size()).first;
+  }
+  *out = tt.base + it->second;
   return HDC_OK;
 }
 
@@ -353,13 +402,15 @@ static hdc_status reduce_common(const hdc_functor* f, const hdc_functor* fm, hdc
   }
   const int op = fused ? HDC_OP_MAP_REDUCE : f->id == HDC_FN_PRODUCT ? HDC_OP_DOT : HDC_OP_TRANSFORM_REDUCE;
   const Tuning t = tuning_for(op, dt, acc, n);
+  uint64_t* ticket = nullptr;
+  if (t.passes == 1) HDC_TRY(ticket_for(ws, &ticket));
 
-  if (!fused) return run_reduce(*f, dt, x, z, n, acc, out, ws, t, st);
+  if (!fused) return run_reduce(*f, dt, x, z, n, acc, out, ws, ticket, t, st);
   switch (dt) {
-    case HDC_F32: return run_map_reduce_f32(*fm, *f, x, y, n, acc, out, ws, t, st);
-    case HDC_F16: return run_map_reduce_f16(*fm, *f, x, y, n, acc, out, ws, t, st);
-    case HDC_BF16: return run_map_reduce_bf16(*fm, *f, x, y, n, acc, out, ws, t, st);
-    case HDC_I32: return run_map_reduce_i32(*fm, *f, x, y, n, acc, out, ws, t, st);
+    case HDC_F32: return run_map_reduce_f32(*fm, *f, x, y, n, acc, out, ws, ticket, t, st);
+    case HDC_F16: return run_map_reduce_f16(*fm, *f, x, y, n, acc, out, ws, ticket, t, st);
+    case HDC_BF16: return run_map_reduce_bf16(*fm, *f, x, y, n, acc, out, ws, ticket, t, st);
+    case HDC_I32: return run_map_reduce_i32(*fm, *f, x, y, n, acc, out, ws, ticket, t, st);
     default: return fail(HDC_ERR_UNSUPPORTED, "dtype %d is not provided", (int)dt);
   }
 }
@@ -420,7 +471,7 @@ hdc_status hdc_segmented_reduce(const hdc_functor* f, hdc_dtype dt, const void* 
     if (e != hipSuccess) return fail(HDC_ERR_HIP, "reading offsets[S]: %s", hipGetErrorString(e));
     if (total < 0 || total / kMinChunk >= INT32_MAX / 2)
       return fail(HDC_ERR_INVALID_ARGUMENT, "offsets[S] = %lld is out of range", (long long)total);
-    cap_bytes = seg_layout(total, num_segments, kMinChunk).bytes;
+    cap_bytes = seg_workspace_bytes(total, num_segments);
     HDC_TRY(resolve_workspace(nullptr, 0, cap_bytes, st, &ws));
     total_bound = total;
   }
@@ -606,7 +657,7 @@ hdc_status hdc_workspace_size(int op, hdc_dtype dt, hdc_accum acc, int64_t n, in
     case HDC_OP_SEGMENTED_REDUCE:
       if (n / kMinChunk >= INT32_MAX / 2 || num_segments >= INT32_MAX)
         return fail(HDC_ERR_INVALID_ARGUMENT, "sizes too large");
-      *bytes = seg_layout(n, num_segments, kMinChunk).bytes;  // enough for every chunk setting
+      *bytes = seg_workspace_bytes(n, num_segments);  // enough for every schedule and chunk setting
       return HDC_OK;
   }
   return fail(HDC_ERR_INVALID_ARGUMENT, "unknown op %d", op);
@@ -650,6 +701,7 @@ hdc_status hdc_set_tuning(int op, hdc_dtype dt, hdc_accum acc, int bucket, const
     if (t->chunk) n.chunk = t->chunk;
     if (t->small_seg) n.small_seg = t->small_seg;
     if (t->seg_per_wave) n.seg_per_wave = t->seg_per_wave;
+    if (t->passes) n.passes = t->passes;
     if (!valid_tuning(n)) return fail(HDC_ERR_INVALID_ARGUMENT, "tuning values out of range");
     upd[b] = n;
   }
@@ -670,6 +722,7 @@ hdc_status hdc_get_tuning(int op, hdc_dtype dt, hdc_accum acc, int bucket, hdc_t
   t->chunk = c.chunk;
   t->small_seg = c.small_seg;
   t->seg_per_wave = c.seg_per_wave;
+  t->passes = c.passes;
   return HDC_OK;
 }
 

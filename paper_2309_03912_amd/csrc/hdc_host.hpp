@@ -34,6 +34,9 @@ struct Tuning {
   int chunk = 4096;
   int small_seg = 128;
   int seg_per_wave = 8;
+  // reductions: 1 = one launch (the last block folds), 2 = two launches;
+  // segmented reduce: 1 = tiled schedule, 2 = planned schedule
+  int passes = 2;
 };
 
 
@@ -102,6 +105,19 @@ constexpr int64_t seg_capacity(size_t bytes, int64_t S) {
   int64_t c = 1 + (int64_t)((bytes - fixed + 1024) / (sizeof(SegPiece) + kPartialBytes));
   while (c > 1 && seg_layout_cap(c, S).bytes > bytes) --c;
   return c;
+}
+
+// Workspace of the tiled schedule for segments holding at most `total`
+// elements: two arrays of one 32-byte slot per tile, tiles of at least
+// kMinChunk elements (the head joins the first tile, the tail the last).
+constexpr size_t seg_tiles_bytes(int64_t total) {
+  return 2 * round_up((size_t)(total / kMinChunk + 2) * kPartialBytes, 256);
+}
+
+// Workspace of a segmented reduce for either schedule.
+constexpr size_t seg_workspace_bytes(int64_t total, int64_t S) {
+  const size_t a = seg_layout(total, S, kMinChunk).bytes, b = seg_tiles_bytes(total);
+  return a > b ? a : b;
 }
 
 // The largest segment total that `bytes` serves at every chunk length (what
@@ -189,17 +205,23 @@ constexpr int64_t batch_chunk_vecs(const Tuning& t, int kvec) {
 // Per-family launchers (one translation unit each).
 hdc_status run_map(const hdc_functor& f, hdc_dtype dt, const void* x, void* y, int64_t n, const Tuning& t,
                    hipStream_t st);
+// `ticket`: NULL for the two-launch form, else a counter for the one-launch
+// form (see launch_reduce).
 hdc_status run_reduce(const hdc_functor& f, hdc_dtype dt, const void* x, const void* z, int64_t n, hdc_accum acc,
-                      void* out, void* ws, const Tuning& t, hipStream_t st);
+                      void* out, void* ws, uint64_t* ticket, const Tuning& t, hipStream_t st);
 // Fused map + reduce, one translation unit per storage type.
 hdc_status run_map_reduce_f32(const hdc_functor& fm, const hdc_functor& f, const void* x, void* y, int64_t n,
-                              hdc_accum acc, void* out, void* ws, const Tuning& t, hipStream_t st);
+                              hdc_accum acc, void* out, void* ws, uint64_t* ticket, const Tuning& t,
+                              hipStream_t st);
 hdc_status run_map_reduce_f16(const hdc_functor& fm, const hdc_functor& f, const void* x, void* y, int64_t n,
-                              hdc_accum acc, void* out, void* ws, const Tuning& t, hipStream_t st);
+                              hdc_accum acc, void* out, void* ws, uint64_t* ticket, const Tuning& t,
+                              hipStream_t st);
 hdc_status run_map_reduce_bf16(const hdc_functor& fm, const hdc_functor& f, const void* x, void* y, int64_t n,
-                               hdc_accum acc, void* out, void* ws, const Tuning& t, hipStream_t st);
+                               hdc_accum acc, void* out, void* ws, uint64_t* ticket, const Tuning& t,
+                               hipStream_t st);
 hdc_status run_map_reduce_i32(const hdc_functor& fm, const hdc_functor& f, const void* x, void* y, int64_t n,
-                              hdc_accum acc, void* out, void* ws, const Tuning& t, hipStream_t st);
+                              hdc_accum acc, void* out, void* ws, uint64_t* ticket, const Tuning& t,
+                              hipStream_t st);
 // `ws_bytes`: the workspace's size, which sets the work-list capacity.
 hdc_status run_segmented(const hdc_functor& f, hdc_dtype dt, const void* x, const int64_t* off, int64_t nseg,
                          hdc_accum acc, void* out, void* ws, size_t ws_bytes, const Tuning& t, hipStream_t st);

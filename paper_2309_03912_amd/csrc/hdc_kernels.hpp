@@ -229,6 +229,112 @@ __global__ __launch_bounds__(1024) void map_kernel(F f, const elem_t<S>* x, elem
 }
 
 // ---------------------------------------------------------------------------
+// Final fold of the per-block partials, in an order that does not depend on
+// the block that runs it: 256 virtual threads, virtual thread v folding
+// partials v, v + 256, v + 512, ... in index order; each virtual wavefront
+// of 64 is reduced by wave_reduce and the four wavefront totals are folded
+// in wavefront order.  A 256-thread block runs one virtual wavefront per
+// wavefront; a smaller block runs several per wavefront.  The result is
+// written to `out`:
+//   PlainAcc -> float (fp32 sum); CompAcc -> double (fp64 sum of s + c, or of
+//   s alone when s is not finite: TwoSum of an infinity yields NaN in c);
+//   ExactAcc -> double (the exact 128-bit total rounded once);
+//   IntAcc -> int64 (wrapping).
+// ---------------------------------------------------------------------------
+
+struct AddF32 { __device__ float operator()(float a, float b) const { return a + b; } };
+struct AddF64 { __device__ double operator()(double a, double b) const { return a + b; } };
+struct AddU64 { __device__ uint64_t operator()(uint64_t a, uint64_t b) const { return a + b; } };
+
+template <class Acc> struct FinalFold;
+template <> struct FinalFold<PlainAcc> {
+  using V = float;
+  using Op = AddF32;
+  __device__ static V term(const PlainAcc& p) { return p.s; }
+  __device__ static V invalid() { return __builtin_nanf(""); }
+  __device__ static void write(void* out, V v) { *static_cast<float*>(out) = v; }
+};
+template <> struct FinalFold<CompAcc> {
+  using V = double;
+  using Op = AddF64;
+  __device__ static V invalid() { return __builtin_nan(""); }
+  __device__ static V term(const CompAcc& p) {
+    return __builtin_isfinite(p.s) ? (double)p.s + (double)p.c : (double)p.s;
+  }
+  __device__ static void write(void* out, V v) { *static_cast<double*>(out) = v; }
+};
+template <> struct FinalFold<IntAcc> {
+  using V = uint64_t;
+  using Op = AddU64;
+  __device__ static V term(const IntAcc& p) { return p.s; }
+  __device__ static V invalid() { return (uint64_t)INT64_MIN; }
+  __device__ static void write(void* out, V v) { *static_cast<int64_t*>(out) = (int64_t)v; }
+};
+template <> struct FinalFold<ExactAcc> {
+  using V = ExactAcc;
+  using Op = MergeOp<ExactAcc>;
+  __device__ static V term(const ExactAcc& p) { return p; }
+  __device__ static V invalid() {
+    ExactAcc a = ExactAcc::zero();
+    a.nf = __builtin_nanf("");
+    return a;
+  }
+  __device__ static void write(void* out, const V& v) { *static_cast<double*>(out) = v.value(); }
+};
+
+constexpr int kFoldThreads = 256;
+
+// Every thread of the block must call this (it synchronises the block);
+// `lds` holds kFoldThreads / 64 values; get(i) returns partial i.
+template <class Acc, class Get>
+__device__ __forceinline__ void fold_partials(Get get, int G, void* out, typename FinalFold<Acc>::V* lds) {
+  using FF = FinalFold<Acc>;
+  using V = typename FF::V;
+  const typename FF::Op op{};
+  constexpr int kVW = kFoldThreads / 64;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int vw = wid; vw < kVW; vw += nw) {
+    V s{};
+    if constexpr (std::is_same_v<Acc, ExactAcc>) s = ExactAcc::zero();
+    for (int i = vw * 64 + lane; i < G; i += kFoldThreads) s = op(s, FF::term(get(i)));
+    const V w = wave_reduce(s, op);
+    if (lane == 0) lds[vw] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    V r = lds[0];
+#pragma unroll
+    for (int i = 1; i < kVW; ++i) r = op(r, lds[i]);
+    FF::write(out, r);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One-launch fold.  A 64-bit ticket holds (epoch << 32 | arrivals).  Every
+// block publishes its partial as sizeof(Acc) / 4 words of 64 bits, each
+// (epoch << 32 | one 32-bit word of the fold state), by single-copy-atomic
+// stores, then counts itself on the ticket.  The block that arrives last
+// reads every word until it carries the launch's epoch (so no fence orders a
+// value against a separate flag), folds the partials, and moves the ticket
+// to the next epoch with 0 arrivals.  A word keeps its tag until rewritten,
+// so a stale word could only pass for a fresh one after 2^32 launches on the
+// same workspace.
+// ---------------------------------------------------------------------------
+
+template <class Acc>
+constexpr int kAccWords = (int)(sizeof(Acc) / 4);
+
+template <class Acc>
+__device__ __forceinline__ void publish_partial(uint64_t* slots, int64_t i, const Acc& a, uint32_t epoch) {
+  uint32_t w[kAccWords<Acc>];
+  __builtin_memcpy(w, &a, sizeof(Acc));
+#pragma unroll
+  for (int k = 0; k < kAccWords<Acc>; ++k)
+    __hip_atomic_store(slots + i * kAccWords<Acc> + k, ((uint64_t)epoch << 32) | w[k], __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
 // transform_reduce pass 1: every block folds its share into one partial.
 // Each lane keeps kVec independent fold states (one per vector component);
 // they are merged in component order, then across the wavefront (DPP), then
@@ -240,7 +346,8 @@ __global__ __launch_bounds__(1024) void map_kernel(F f, const elem_t<S>* x, elem
 template <class F, class S, class Acc, int U, bool kVector, class FM = Identity, bool kMap = false>
   requires device_callable<F> && device_callable<FM>
 __global__ __launch_bounds__(1024) void reduce_kernel(F f, const elem_t<S>* x, const elem_t<S>* z, Range r,
-                                                      Acc* partials, FM fm = FM{}, elem_t<S>* y = nullptr) {
+                                                      Acc* partials, uint64_t* ticket, void* out, FM fm = FM{},
+                                                      elem_t<S>* y = nullptr) {
   __shared__ Acc lds[kMaxWaves];
   const int64_t B = blockDim.x;
   const int64_t tid = threadIdx.x;
@@ -381,53 +488,83 @@ __global__ __launch_bounds__(1024) void reduce_kernel(F f, const elem_t<S>* x, c
 #pragma unroll
   for (int k = 1; k < K; ++k) t = Acc::merge(t, outer[k]);
   t = block_reduce(t, MergeOp<Acc>{}, lds);
-  if (tid == 0) partials[blockIdx.x] = t;
+  if (!ticket) {
+    if (tid == 0) partials[blockIdx.x] = t;
+  } else {
+    // One launch: the block that arrives last folds every partial (the
+    // workspace holds the tagged words instead of plain partials).
+    __shared__ int last;
+    __shared__ uint32_t epoch_sh;
+    __shared__ typename FinalFold<Acc>::V fold_lds[kFoldThreads / 64];
+    uint64_t* slots = reinterpret_cast<uint64_t*>(partials);
+    if (tid == 0) {
+      const uint32_t epoch = (uint32_t)(__hip_atomic_load(ticket, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32);
+      publish_partial(slots, blockIdx.x, t, epoch);
+      const uint64_t old = __hip_atomic_fetch_add(ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      last = (uint32_t)old == gridDim.x - 1;
+      epoch_sh = epoch;
+    }
+    __syncthreads();
+    if (last) {
+      // Stage every tagged word in LDS (dynamic, gridDim.x * kAccWords words):
+      // eight independent loads per thread per round, a word re-read only
+      // while it lacks the epoch; then fold from LDS in the fixed order.
+      extern __shared__ uint32_t stage[];
+      const uint32_t epoch = epoch_sh;
+      const int nw = (int)gridDim.x * kAccWords<Acc>;
+      bool ok = true;
+      for (int base = 0; base < nw; base += 8 * (int)B) {
+        uint64_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int k = base + u * (int)B + (int)tid;
+          v[u] = k < nw ? __hip_atomic_load(slots + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                        : (uint64_t)epoch << 32;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int k = base + u * (int)B + (int)tid;
+          for (int polls = 0; (uint32_t)(v[u] >> 32) != epoch; ++polls) {
+            if (polls == (1 << 20)) {
+              ok = false;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+            v[u] = __hip_atomic_load(slots + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+          if (k < nw) stage[k] = (uint32_t)v[u];
+        }
+      }
+      __shared__ int all_ok;
+      if (tid == 0) all_ok = 1;
+      __syncthreads();
+      if (!ok) all_ok = 0;
+      __syncthreads();
+      fold_partials<Acc>(
+          [&](int i) {
+            Acc a;
+            __builtin_memcpy(&a, stage + (int64_t)i * kAccWords<Acc>, sizeof(Acc));
+            return a;
+          },
+          (int)gridDim.x, out, fold_lds);
+      if (tid == 0) {
+        if (!all_ok) FinalFold<Acc>::write(out, FinalFold<Acc>::invalid());
+        // arrivals back to 0, next epoch
+        __hip_atomic_fetch_add(ticket, (1ull << 32) - gridDim.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
-// transform_reduce pass 2: one block folds the G partials in index order
-// (thread-strided, then the fixed block reduction) and writes the result.
-//   PlainAcc -> float (fp32 sum); CompAcc -> double (fp64 sum of s + c, or of
-//   s alone when s is not finite: TwoSum of an infinity yields NaN in c);
-//   ExactAcc -> double (the exact 128-bit total rounded once);
-//   IntAcc -> int64 (wrapping).
+// transform_reduce pass 2 (the two-launch form): one block of kFoldThreads
+// threads folds the G partials (fold_partials) and writes the result.
 // ---------------------------------------------------------------------------
 
-struct AddF32 { __device__ float operator()(float a, float b) const { return a + b; } };
-struct AddF64 { __device__ double operator()(double a, double b) const { return a + b; } };
-struct AddU64 { __device__ uint64_t operator()(uint64_t a, uint64_t b) const { return a + b; } };
-
 template <class Acc>
-__global__ __launch_bounds__(256) void reduce_final_kernel(const Acc* partials, int G, void* out) {
-  const int tid = threadIdx.x;
-  if constexpr (std::is_same_v<Acc, PlainAcc>) {
-    __shared__ float lds[kMaxWaves];
-    float s = 0.0f;
-    for (int i = tid; i < G; i += blockDim.x) s += partials[i].s;
-    s = block_reduce(s, AddF32{}, lds);
-    if (tid == 0) *static_cast<float*>(out) = s;
-  } else if constexpr (std::is_same_v<Acc, CompAcc>) {
-    __shared__ double lds[kMaxWaves];
-    double s = 0.0;
-    for (int i = tid; i < G; i += blockDim.x) {
-      const CompAcc p = partials[i];
-      s += __builtin_isfinite(p.s) ? (double)p.s + (double)p.c : (double)p.s;
-    }
-    s = block_reduce(s, AddF64{}, lds);
-    if (tid == 0) *static_cast<double*>(out) = s;
-  } else if constexpr (std::is_same_v<Acc, ExactAcc>) {
-    __shared__ ExactAcc lds[kMaxWaves];
-    ExactAcc s = ExactAcc::zero();
-    for (int i = tid; i < G; i += blockDim.x) s = ExactAcc::merge(s, partials[i]);
-    s = block_reduce(s, MergeOp<ExactAcc>{}, lds);
-    if (tid == 0) *static_cast<double*>(out) = s.value();
-  } else {
-    __shared__ uint64_t lds[kMaxWaves];
-    uint64_t s = 0;
-    for (int i = tid; i < G; i += blockDim.x) s += partials[i].s;
-    s = block_reduce(s, AddU64{}, lds);
-    if (tid == 0) *static_cast<int64_t*>(out) = (int64_t)s;
-  }
+__global__ __launch_bounds__(kFoldThreads) void reduce_final_kernel(const Acc* partials, int G, void* out) {
+  __shared__ typename FinalFold<Acc>::V lds[kFoldThreads / 64];
+  fold_partials<Acc>([&](int i) { return partials[i]; }, G, out, lds);
 }
 
 }  // namespace hdc

@@ -38,13 +38,18 @@ hdc_status launch_map(const F& f, const void* x, void* y, int64_t n, const Tunin
 
 template <class Acc>
 hdc_status launch_final(const Acc* partials, int64_t g, void* out, hipStream_t st) {
-  reduce_final_kernel<Acc><<<dim3(1), dim3(256), 0, st>>>(partials, (int)g, out);
+  reduce_final_kernel<Acc><<<dim3(1), dim3(kFoldThreads), 0, st>>>(partials, (int)g, out);
   return check_launch("final combine launch");
 }
 
+// `ticket`: a 64-bit counter (epoch, arrivals) with 0 arrivals that no other
+// work uses until this call completes; with it the reduction is one launch
+// (its last block folds the partials), without it (NULL) two launches.  Both
+// fold in the same order, so they give the same bits.
 template <class F, class S, class Acc, class FM = Identity, bool kMap = false>
 hdc_status launch_reduce(const F& f, const void* x, const void* z, int64_t n, void* out, void* ws,
-                         const Tuning& t, hipStream_t st, const FM& fm = FM{}, void* y = nullptr) {
+                         uint64_t* ticket, const Tuning& t, hipStream_t st, const FM& fm = FM{},
+                         void* y = nullptr) {
   using T = typename S::T;
   int cus = 0;
   HDC_TRY(compute_units(&cus));
@@ -55,14 +60,21 @@ hdc_status launch_reduce(const F& f, const void* x, const void* z, int64_t n, vo
   const int64_t units = vec ? r.nvec : n;
   const int64_t g = grid_for(units, (int64_t)t.block * t.unroll, cus, t);
   Acc* partials = static_cast<Acc*>(ws);
+  // The one-launch form keeps 8 bytes per 32-bit word of every partial in
+  // the workspace and stages the words in LDS (at most kMaxStageBytes); a
+  // larger grid takes two launches.
+  constexpr size_t kMaxStageBytes = 32768;
+  const size_t stage = (size_t)g * kAccWords<Acc> * 4;
+  if (ticket && (2 * stage > reduce_workspace_bytes() || stage > kMaxStageBytes)) ticket = nullptr;
+  const size_t dyn = ticket ? stage : 0;
   auto go = [&](auto U) {
     constexpr int kU = decltype(U)::value;
     if (vec)
-      reduce_kernel<F, S, Acc, kU, true, FM, kMap><<<dim3((unsigned)g), dim3(t.block), 0, st>>>(
-          f, (const T*)x, (const T*)z, r, partials, fm, (T*)y);
+      reduce_kernel<F, S, Acc, kU, true, FM, kMap><<<dim3((unsigned)g), dim3(t.block), dyn, st>>>(
+          f, (const T*)x, (const T*)z, r, partials, ticket, out, fm, (T*)y);
     else
-      reduce_kernel<F, S, Acc, kU, false, FM, kMap><<<dim3((unsigned)g), dim3(t.block), 0, st>>>(
-          f, (const T*)x, (const T*)z, r, partials, fm, (T*)y);
+      reduce_kernel<F, S, Acc, kU, false, FM, kMap><<<dim3((unsigned)g), dim3(t.block), dyn, st>>>(
+          f, (const T*)x, (const T*)z, r, partials, ticket, out, fm, (T*)y);
   };
   switch (t.unroll) {
     case 1: go(std::integral_constant<int, 1>{}); break;
@@ -71,6 +83,7 @@ hdc_status launch_reduce(const F& f, const void* x, const void* z, int64_t n, vo
     default: go(std::integral_constant<int, 8>{}); break;
   }
   HDC_TRY(check_launch("reduce kernel launch"));
+  if (ticket) return HDC_OK;
   return launch_final<Acc>(partials, g, out, st);
 }
 
@@ -136,10 +149,49 @@ inline hdc_status launch_exact_f16_dot(const void* x, const void* z, int64_t n, 
   return check_launch("exact fp16 dot final launch");
 }
 
+// Tiled schedule of the segmented reduce (t.passes == 1): the tile pass and
+// the combine of segments that span tiles.  The workspace holds two slot
+// arrays (`first`, `last`) of one 32-byte fold state per tile.
+template <class F, class S, class Acc>
+hdc_status launch_seg_tiles(const F& f, const void* x, const int64_t* off, int64_t nseg, void* out, void* ws,
+                            size_t ws_bytes, const Tuning& t, hipStream_t st) {
+  using T = typename S::T;
+  static_assert(sizeof(Acc) <= kPartialBytes, "a tile slot holds 32 bytes");
+  int cus = 0;
+  HDC_TRY(compute_units(&cus));
+  const size_t half = ws_bytes / 2 / 256 * 256;
+  SegTiles tl;
+  tl.first = ws;
+  tl.last = static_cast<char*>(ws) + half;
+  tl.cap = (int64_t)(half / kPartialBytes);
+  tl.tile_vecs = t.chunk / S::kVec;
+  const int64_t wpb = t.block / 64;
+  int64_t g = (int64_t)cus * t.grid_mult;
+  const int64_t need = (tl.cap + wpb - 1) / wpb;  // never more wavefronts than tiles fit the workspace
+  if (g > need) g = need;
+  if (g < 1) g = 1;
+  auto go = [&](auto U) {
+    constexpr int kU = decltype(U)::value;
+    seg_tiles_kernel<F, S, Acc, kU><<<dim3((unsigned)g), dim3(t.block), 0, st>>>(f, (const T*)x, off, nseg, tl, out);
+  };
+  switch (t.unroll) {
+    case 1: go(std::integral_constant<int, 1>{}); break;
+    case 2: go(std::integral_constant<int, 2>{}); break;
+    case 4: go(std::integral_constant<int, 4>{}); break;
+    default: go(std::integral_constant<int, 8>{}); break;
+  }
+  HDC_TRY(check_launch("segmented tile launch"));
+  int64_t gc = (nseg + 255) / 256;  // one wavefront per 64 segments
+  if (gc > (int64_t)cus * 8) gc = (int64_t)cus * 8;
+  seg_tiles_combine_kernel<S, Acc><<<dim3((unsigned)gc), dim3(256), 0, st>>>((const T*)x, off, nseg, tl, out);
+  return check_launch("segmented tile combine launch");
+}
+
 template <class F, class S, class Acc>
 hdc_status launch_segmented(const F& f, const void* x, const int64_t* off, int64_t nseg, void* out, void* ws,
                             size_t ws_bytes, const Tuning& t, hipStream_t st) {
   using T = typename S::T;
+  if (t.passes == 1) return launch_seg_tiles<F, S, Acc>(f, x, off, nseg, out, ws, ws_bytes, t, st);
   int cus = 0;
   HDC_TRY(compute_units(&cus));
   const int64_t cap = seg_capacity(ws_bytes, nseg);

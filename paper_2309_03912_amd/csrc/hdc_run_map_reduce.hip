@@ -11,14 +11,14 @@
 namespace hdc {
 
 hdc_status HDC_MR_NAME(const hdc_functor& fm, const hdc_functor& f, const void* x, void* y, int64_t n,
-                       hdc_accum acc, void* out, void* ws, const Tuning& t, hipStream_t st) {
+                       hdc_accum acc, void* out, void* ws, uint64_t* ticket, const Tuning& t, hipStream_t st) {
   using S = HDC_MR_STORAGE;
   if constexpr (std::is_same_v<S, I32>) {
     (void)acc;
     return with_int_fn(f, [&](auto fn) {
       return with_int_fn(fm, [&](auto mfn) {
-        return launch_reduce<decltype(fn), I32, IntAcc, decltype(mfn), true>(fn, x, nullptr, n, out, ws, t, st, mfn,
-                                                                             y);
+        return launch_reduce<decltype(fn), I32, IntAcc, decltype(mfn), true>(fn, x, nullptr, n, out, ws, ticket, t,
+                                                                             st, mfn, y);
       });
     });
   } else {
@@ -29,8 +29,8 @@ hdc_status HDC_MR_NAME(const hdc_functor& fm, const hdc_functor& f, const void* 
           if constexpr (FM::binary)
             return fail(HDC_ERR_UNSUPPORTED, "PRODUCT cannot be mapped");
           else
-            return launch_reduce<Identity, F16, ExactAcc, FM, true>(Identity{}, x, nullptr, n, out, ws, t, st, mfn,
-                                                                   y);
+            return launch_reduce<Identity, F16, ExactAcc, FM, true>(Identity{}, x, nullptr, n, out, ws, ticket, t,
+                                                                   st, mfn, y);
         });
     }
     return with_float_fn(f, [&](auto fn) -> hdc_status {
@@ -44,8 +44,8 @@ hdc_status HDC_MR_NAME(const hdc_functor& fm, const hdc_functor& f, const void* 
             return fail(HDC_ERR_UNSUPPORTED, "PRODUCT cannot be mapped");
           } else {
             if (acc == HDC_ACC_COMPENSATED)
-              return launch_reduce<F, S, CompAcc, FM, true>(fn, x, nullptr, n, out, ws, t, st, mfn, y);
-            return launch_reduce<F, S, PlainAcc, FM, true>(fn, x, nullptr, n, out, ws, t, st, mfn, y);
+              return launch_reduce<F, S, CompAcc, FM, true>(fn, x, nullptr, n, out, ws, ticket, t, st, mfn, y);
+            return launch_reduce<F, S, PlainAcc, FM, true>(fn, x, nullptr, n, out, ws, ticket, t, st, mfn, y);
           }
         });
       }

@@ -153,6 +153,31 @@ __device__ __forceinline__ void store_result(void* out, int64_t j, const Acc& a)
     static_cast<int64_t*>(out)[j] = (int64_t)a.s;
 }
 
+// Fold items get(0), ..., get(m - 1) with one wavefront: lane l folds items
+// l, l + 64, ... in order, eight loads in flight, then the lanes meet in
+// wave_reduce.  Every lane must be active; every lane returns the total.
+template <class V, class Op, class Get>
+__device__ __forceinline__ V wave_fold_items(Get get, int64_t m, int lane, Op op, V zero) {
+  V acc = zero;
+  for (int64_t base = 0; base < m; base += 8 * 64) {
+    V v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t k = base + u * 64 + lane;
+      v[u] = k < m ? get(k) : zero;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (base + u * 64 + lane < m) acc = op(acc, v[u]);
+  }
+  return wave_reduce(acc, op);
+}
+
+// The fp64 value of a compensated pair (s alone when s is not finite).
+__device__ __forceinline__ double comp_value(const CompAcc& q) {
+  return __builtin_isfinite(q.s) ? (double)q.s + (double)q.c : (double)q.s;
+}
+
 // Fold x[s, e) with one wavefront; every lane returns the total.
 template <class F, class S, class Acc, int U>
 __device__ __forceinline__ Acc wave_fold_range(const F& f, const elem_t<S>* __restrict__ x, int64_t s, int64_t e,
@@ -350,24 +375,341 @@ __global__ __launch_bounds__(256) void seg_combine_kernel(const int64_t* __restr
     const int64_t L = off[j + 1] - off[j];
     const int64_t np = (L + p.chunk - 1) / p.chunk;
     const int64_t base = p.long_base[j];
+    const int64_t m = base >= 0 ? (base + np <= p.cap_partials ? np : p.cap_partials - base) : 0;
     if constexpr (std::is_same_v<Acc, CompAcc>) {
       // fp64 final combine of the compensated pairs
-      double d = 0.0;
-      if (base >= 0)
-        for (int64_t k = lane; k < np; k += 64)
-          if (base + k < p.cap_partials) {
-            const CompAcc q = partials[base + k];
-            d += __builtin_isfinite(q.s) ? (double)q.s + (double)q.c : (double)q.s;
-          }
-      d = wave_reduce(d, AddF64{});
+      const double d = wave_fold_items<double>([&](int64_t k) { return comp_value(partials[base + k]); }, m, lane,
+                                               AddF64{}, 0.0);
       if (lane == 0) static_cast<double*>(out)[j] = d;
     } else {
-      Acc a = Acc::zero();
-      if (base >= 0)
-        for (int64_t k = lane; k < np; k += 64)
-          if (base + k < p.cap_partials) a = Acc::merge(a, partials[base + k]);
-      a = wave_reduce(a, MergeOp<Acc>{});
+      const Acc a = wave_fold_items<Acc>([&](int64_t k) { return partials[base + k]; }, m, lane, MergeOp<Acc>{},
+                                         Acc::zero());
       if (lane == 0) store_result<Acc>(out, j, a);
+    }
+  }
+}
+
+// ===========================================================================
+// Tiled schedule.  The element range [off[0], off[S]) is cut into fixed
+// tiles of `tile_vecs` 16-byte vectors, independent of the segments, and
+// every wavefront streams whole tiles (w, w + W, ...) exactly as the plain
+// reduction streams its share: U vectors per lane per step, all loads of a
+// step in flight together.  The segment boundaries inside a tile come from
+// the offsets, 64 at a time in one vector register; each step first adds its
+// terms to the lanes' fold states, and only when a boundary falls inside the
+// step does the wavefront split the step's terms at it, reduce the part that
+// ends there (wave_reduce) and store it.  A segment that starts and ends
+// inside one tile is written to `out` directly.  Otherwise each tile writes
+// its part of that segment to one of two slots (`first`: the segment was open
+// when the tile started; `last`: it started in the tile and runs past its
+// end), and a second small launch folds, in tile order, the parts of every
+// segment that spans tiles (and writes 0 for empty segments).  No plan is
+// built, and the work of every wavefront is the same number of vectors.
+// The unaligned head of the range belongs to the first tile, its tail to the
+// last one.  Everything is a fold of fixed values in a fixed order, so the
+// results are reproducible bit for bit.
+// ===========================================================================
+
+struct SegTiles {
+  void* first;        // per tile: its part of the segment open at its start
+  void* last;         // per tile: its part of a segment starting in it and running past its end
+  int64_t cap;        // tiles the workspace holds
+  int64_t tile_vecs;  // 16-byte vectors per tile
+};
+
+// Geometry of the streamed range, from off[0] and off[S] (read on the device).
+struct TileGeom {
+  int64_t lo;          // off[0]: position 0 of the range
+  int64_t n;           // off[S] - off[0]
+  int64_t head;        // elements before the first 16-byte boundary
+  int64_t nvec;        // whole vectors after the head
+  int64_t tail_start;  // first element after the vectors
+  int64_t ntiles;
+};
+
+template <class S>
+__device__ __forceinline__ TileGeom tile_geom(const elem_t<S>* x, const int64_t* off, int64_t S_,
+                                              int64_t tile_vecs) {
+  TileGeom g{};
+  g.lo = off[0];
+  const int64_t hi = off[S_];
+  g.n = hi > g.lo ? hi - g.lo : 0;
+  const int64_t es = sizeof(elem_t<S>);
+  const int64_t mis = (int64_t)((uintptr_t)(x + g.lo) % 16);
+  int64_t head = mis ? (16 - mis) / es : 0;
+  if (head > g.n) head = g.n;
+  g.head = head;
+  g.nvec = (g.n - head) / S::kVec;
+  g.tail_start = head + g.nvec * S::kVec;
+  g.ntiles = g.n == 0 ? 0 : (g.nvec + tile_vecs - 1) / tile_vecs;
+  if (g.n > 0 && g.ntiles == 0) g.ntiles = 1;
+  return g;
+}
+
+// The tile holding position p (relative to off[0]).
+template <class S>
+__host__ __device__ __forceinline__ int64_t tile_of(const TileGeom& g, int64_t tile_vecs, int64_t p) {
+  if (p < g.head) return 0;
+  const int64_t t = (p - g.head) / (tile_vecs * S::kVec);
+  return t < g.ntiles - 1 ? t : g.ntiles - 1;
+}
+
+template <class F, class S, class Acc, int U>
+struct TileWave {
+  static constexpr int KV = S::kVec;
+  static constexpr int K = U * KV;  // elements per lane per step
+  static constexpr bool kInt = std::is_same_v<S, I32>;
+  using Term = std::conditional_t<kInt, uint64_t, float>;
+
+  const F& f;
+  const elem_t<S>* x;  // x + off[0]
+  const int64_t* off;
+  int64_t S_;
+  const TileGeom& g;
+  SegTiles st;
+  void* out;
+  int lane;
+  int64_t tile;
+  // wavefront-uniform state of the current segment
+  int64_t j;        // the segment holding the next position
+  int64_t nb;       // its end, off[j + 1] - off[0]
+  bool started;     // it starts inside this tile
+  int64_t bbase;    // offsets[bbase + l] are in lane l of `bnd`
+  int64_t bnd;      // a batch of 64 offsets (relative to off[0]); past off[S]: INT64_MAX
+  Acc acc;
+
+  // Find the segment holding position p (relative to off[0]): the last j with
+  // off[j] - off[0] <= p.  Rounds of 64 evenly spaced probes narrow the range
+  // to at most 64 offsets, whose final round is kept as the boundary batch.
+  __device__ void locate(int64_t p) {
+    int64_t lo = 0, len = S_ + 1;  // off[lo] - off[0] <= p; the answer is in [lo, lo + len)
+    while (len > 64) {
+      const int64_t step = (len + 63) / 64;
+      const int64_t idx = lo + (int64_t)lane * step;
+      const bool le = idx < lo + len && off[idx] - g.lo <= p;
+      const int cnt = __builtin_popcountll(__builtin_amdgcn_ballot_w64(le));  // a prefix of the lanes
+      const int64_t nlo = lo + (int64_t)(cnt - 1) * step;
+      len = lo + len - nlo < step ? lo + len - nlo : step;
+      lo = nlo;
+    }
+    load_batch(lo);
+    const int cnt = __builtin_popcountll(__builtin_amdgcn_ballot_w64(lane < len && bnd <= p));
+    j = lo + cnt - 1;
+  }
+
+  __device__ void load_batch(int64_t base) {
+    bbase = base;
+    const int64_t i = base + lane;
+    bnd = i <= S_ ? off[i] - g.lo : INT64_MAX;
+  }
+  // off[i] - off[0] for i in [bbase, ...), from the batch (reloaded when passed)
+  __device__ int64_t bound(int64_t i) {
+    if (i - bbase >= 64) load_batch(i);
+    return read_lane(bnd, (int)(i - bbase));
+  }
+
+  // Store the fold of a segment part that ends inside this tile.
+  __device__ void finish(const Acc& total) {
+    if (lane == 0 && j < S_) {
+      if (started)
+        store_result<Acc>(out, j, total);
+      else
+        static_cast<Acc*>(st.first)[tile] = total;
+    }
+  }
+  // Leave segment j at its end nb: the next non-empty segment starts there.
+  __device__ void advance() {
+    const int64_t b = nb;
+    do {
+      ++j;
+      nb = bound(j + 1);
+    } while (nb == b);
+    started = true;
+  }
+
+  // Add a step's terms.  Term k sits at position ps + rel(k) and exists iff
+  // ok(k); every position of the step lies in [ps, pe), pe - ps < 2^31.
+  template <class Rel, class Ok>
+  __device__ void step(const Term (&t)[K], Rel rel, Ok ok, int64_t ps, int64_t pe) {
+    if (nb >= pe) {  // no boundary inside the step (uniform)
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (ok(k)) acc.add(t[k]);
+      return;
+    }
+    int prev = 0;  // terms before ps + prev are already folded
+    while (nb < pe) {
+      const int end = (int)(nb - ps);
+#pragma unroll
+      for (int k = 0; k < K; ++k) acc.add(ok(k) && rel(k) >= prev && rel(k) < end ? t[k] : Term{});
+      finish(wave_reduce(acc, MergeOp<Acc>{}));
+      acc = Acc::zero();
+      prev = end;
+      advance();
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc.add(ok(k) && rel(k) >= prev ? t[k] : Term{});
+  }
+
+  __device__ void terms(const elem_t<S> (&v)[K], Term (&t)[K]) {
+    if constexpr (kInt) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) t[k] = f.term(v[k]);
+    } else {
+      float w[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) w[k] = S::widen(v[k]);
+      eval_batch(f, w);
+#pragma unroll
+      for (int k = 0; k < K; ++k) t[k] = w[k];
+    }
+  }
+
+  // A step of single elements: lane l takes position p0 + l if below p1.
+  __device__ void scalar_step(int64_t p0, int64_t p1) {
+    const bool mine = p0 + lane < p1;
+    elem_t<S> v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = k == 0 && mine ? x[p0 + lane] : elem_t<S>{};
+    Term t[K];
+    terms(v, t);
+    step(t, [&](int) { return lane; }, [&](int k) { return k == 0 && mine; }, p0, p1);
+  }
+
+  __device__ void run() {
+    const int64_t vb = tile * st.tile_vecs;
+    const int64_t ve = vb + st.tile_vecs < g.nvec ? vb + st.tile_vecs : g.nvec;
+    const bool first_tile = tile == 0, last_tile = tile == g.ntiles - 1;
+    const int64_t ps0 = first_tile ? 0 : g.head + vb * KV;
+    const int64_t pe0 = last_tile ? g.n : g.head + ve * KV;
+    const elem_t<S>* xv = x + g.head;
+    Vec<S> a[U];
+    auto issue = [&](int64_t v0) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t vi = v0 + u * 64 + lane;
+        a[u] = vi < ve ? load16<S>(xv + vi * KV) : Vec<S>{};
+      }
+    };
+    // The first step's loads go out before the search for the segment
+    // holding ps0 (which needs three dependent rounds of offsets).
+    if (vb < ve) issue(vb);
+    locate(ps0);
+    started = read_lane(bnd, (int)(j - bbase)) >= ps0;
+    nb = bound(j + 1);
+    acc = Acc::zero();
+
+    if (first_tile && g.head > 0) scalar_step(0, g.head);
+    for (int64_t v0 = vb; v0 < ve; v0 += 64 * U) {
+      if (v0 != vb) issue(v0);
+      const bool full = v0 + 64 * U <= ve;
+      const int nv = full ? 64 * U : (int)(ve - v0);  // vectors of this step
+      elem_t<S> v[K];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int e = 0; e < KV; ++e) v[u * KV + e] = a[u].e[e];
+      Term t[K];
+      terms(v, t);
+      // term (u, e) is element e of vector v0 + 64 u + lane
+      step(t, [&](int k) { return ((k / KV) * 64 + lane) * KV + k % KV; },
+           [&](int k) { return full || (k / KV) * 64 + lane < nv; }, g.head + v0 * KV, g.head + (v0 + nv) * KV);
+    }
+    if (last_tile && g.tail_start < g.n) scalar_step(g.tail_start, g.n);
+
+    // The segment open at the tile's end: it ends exactly there, or runs on.
+    const Acc total = wave_reduce(acc, MergeOp<Acc>{});
+    if (nb == pe0) {
+      finish(total);
+    } else if (lane == 0) {
+      if (started)
+        static_cast<Acc*>(st.last)[tile] = total;
+      else
+        static_cast<Acc*>(st.first)[tile] = total;
+    }
+  }
+};
+
+template <class F, class S, class Acc, int U>
+  requires device_callable<F>
+__global__ __launch_bounds__(1024) void seg_tiles_kernel(F f, const elem_t<S>* __restrict__ x,
+                                                         const int64_t* __restrict__ off, int64_t S_, SegTiles st,
+                                                         void* out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wpb = blockDim.x >> 6;
+  const int64_t w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * wpb + (threadIdx.x >> 6)));
+  const int64_t W = (int64_t)gridDim.x * wpb;
+  const TileGeom g = tile_geom<S>(x, off, S_, st.tile_vecs);
+  if (g.ntiles > st.cap) {
+    // More tiles than the workspace holds: every segment is folded whole by one wavefront.
+    for (int64_t j = w; j < S_; j += W) {
+      const Acc r = wave_fold_range<F, S, Acc, U>(f, x, off[j], off[j + 1], lane);
+      if (lane == 0) store_result<Acc>(out, j, r);
+    }
+    return;
+  }
+  for (int64_t t = w; t < g.ntiles; t += W) {
+    TileWave<F, S, Acc, U> tw{f, x + g.lo, off, S_, g, st, out, lane, t};
+    tw.run();
+  }
+}
+
+// Segments that span tiles: their parts folded in tile order (the part of
+// the tile where the segment starts, then every later tile's `first` part);
+// empty segments: 0.  Each lane takes one segment; a segment spanning more
+// than kLaneTiles tiles is folded by the whole wavefront (wave_fold_items).
+constexpr int64_t kLaneTiles = 16;
+
+template <class S, class Acc>
+__global__ __launch_bounds__(256) void seg_tiles_combine_kernel(const elem_t<S>* __restrict__ x,
+                                                                const int64_t* __restrict__ off, int64_t S_,
+                                                                SegTiles st, void* out) {
+  const TileGeom g = tile_geom<S>(x, off, S_, st.tile_vecs);
+  if (g.ntiles > st.cap) return;  // the tile pass folded every segment whole
+  const Acc* first = static_cast<const Acc*>(st.first);
+  const Acc* last = static_cast<const Acc*>(st.last);
+  constexpr bool kComp = std::is_same_v<Acc, CompAcc>;
+  // part k of a segment whose first tile is ts
+  auto part = [&](int64_t ts, int64_t k) { return k == 0 ? last[ts] : first[ts + k]; };
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t j0 = wave * 64; j0 < S_; j0 += nwaves * 64) {
+    const int64_t j = j0 + lane;
+    int64_t ts = 0, te = 0;
+    if (j < S_) {
+      const int64_t s = off[j] - g.lo, e = off[j + 1] - g.lo;
+      if (e <= s) {
+        store_result<Acc>(out, j, Acc::zero());
+      } else {
+        ts = tile_of<S>(g, st.tile_vecs, s);
+        te = tile_of<S>(g, st.tile_vecs, e - 1);
+      }
+    }
+    const bool wide = te - ts > kLaneTiles;
+    if (te > ts && !wide) {  // a few tiles: this lane folds them in order
+      if constexpr (kComp) {
+        double d = comp_value(part(ts, 0));
+        for (int64_t k = 1; k <= te - ts; ++k) d += comp_value(part(ts, k));
+        static_cast<double*>(out)[j] = d;
+      } else {
+        Acc a = part(ts, 0);
+        for (int64_t k = 1; k <= te - ts; ++k) a = Acc::merge(a, part(ts, k));
+        store_result<Acc>(out, j, a);
+      }
+    }
+    for (uint64_t mask = __builtin_amdgcn_ballot_w64(wide); mask; mask &= mask - 1) {  // uniform
+      const int b = __builtin_ctzll(mask);
+      const int64_t bts = read_lane(ts, b), m = read_lane(te, b) - bts + 1;
+      if constexpr (kComp) {
+        const double d = wave_fold_items<double>([&](int64_t k) { return comp_value(part(bts, k)); }, m, lane,
+                                                 AddF64{}, 0.0);
+        if (lane == 0) static_cast<double*>(out)[j0 + b] = d;
+      } else {
+        const Acc a = wave_fold_items<Acc>([&](int64_t k) { return part(bts, k); }, m, lane, MergeOp<Acc>{},
+                                           Acc::zero());
+        if (lane == 0) store_result<Acc>(out, j0 + b, a);
+      }
     }
   }
 }

@@ -190,13 +190,22 @@ def test_tuning_roundtrip_and_cache(tmp_path):
     p.write_text("# op dtype acc bucket block unroll grid_mult chunk small_seg spw\n1 2 1 3 1024 8 4 4096 32 16\n")
     hdc.load_tuning(str(p))
     assert hdc.get_tuning(1, 2, 1, 3) == {"block": 1024, "unroll": 8, "grid_mult": 4, "chunk": 4096,
-                                          "small_seg": 32, "seg_per_wave": 16}
+                                          "small_seg": 32, "seg_per_wave": 16, "passes": 2}
+    p.write_text("1 2 1 3 1024 8 4 4096 32 16 1\n")  # with the optional passes field
+    hdc.load_tuning(str(p))
+    assert hdc.get_tuning(1, 2, 1, 3)["passes"] == 1
+    p.write_text("1 2 1 3 1024 8 4 4096 32 16 3\n")
+    with pytest.raises(hdc.HdcError):
+        hdc.load_tuning(str(p))
     p.write_text("1 2 1 3 1000 8 4 4096 32 16\n")
     with pytest.raises(hdc.HdcError):
         hdc.load_tuning(str(p))
     hdc.load_tuning(str(tmp_path / "missing.txt"))  # a missing cache keeps the defaults
     hdc.set_tuning(hdc.OP_MAP, hdc.F16, hdc.ACC_PLAIN, block=256, unroll=4)
     hdc.set_tuning(1, 2, 1, block=256, unroll=4, grid_mult=8, chunk=4096, small_seg=128, seg_per_wave=8)
+    hdc.set_tuning(1, 2, 1, passes=2)
+    with pytest.raises(hdc.HdcError):
+        hdc.set_tuning(1, 2, 1, passes=3)
     with pytest.raises(hdc.HdcError):
         hdc.set_tuning(2, 0, 0, seg_per_wave=3)
     with pytest.raises(hdc.HdcError):

@@ -42,6 +42,22 @@ def edge_lengths(seed=0, count=600):
     return torch.tensor(L, dtype=torch.int64)
 
 
+SEG_CLASSES = [(dt, acc) for dt in (hdc.F32, hdc.F16, hdc.BF16) for acc in (hdc.ACC_PLAIN, hdc.ACC_COMPENSATED)] + \
+    [(hdc.I32, hdc.ACC_EXACT_INT)]
+
+
+@pytest.fixture(autouse=True, params=[1, 2], ids=["tiled", "planned"])
+def schedule(request):
+    """Every test runs under both schedules of the segmented reduce (tuning field `passes`)."""
+    saved = {(dt, acc, b): hdc.get_tuning(hdc.OP_SEGMENTED_REDUCE, dt, acc, b)
+             for dt, acc in SEG_CLASSES for b in range(hdc.BUCKETS)}
+    for dt, acc in SEG_CLASSES:
+        hdc.set_tuning(hdc.OP_SEGMENTED_REDUCE, dt, acc, -1, passes=request.param)
+    yield request.param
+    for (dt, acc, b), t in saved.items():
+        hdc.set_tuning(hdc.OP_SEGMENTED_REDUCE, dt, acc, b, **t)
+
+
 def check_segments(got, ref, what):
     got = got.cpu().double().numpy()
     exact, A = ref["exact"], ref["abs_sum"]
@@ -197,3 +213,29 @@ def test_segmented_library_workspace_reads_the_total():
                                         torch.cuda.current_stream().cuda_stream)
     assert st == hdc.OK, hdc.lib().hdc_last_error()
     check_segments(out, oracle.segmented(FNS["horner"], x, off), "library workspace")
+
+
+@pytest.mark.parametrize("chunk", [1024, 4096])
+@pytest.mark.parametrize("shift", [0, 1, 3])
+def test_segmented_boundaries_on_and_around_tile_edges(chunk, shift):
+    """Segments of exactly one tile, one tile +- 1, several tiles, runs of empty segments at tile edges,
+    and a first segment that starts inside the range (offsets[0] > 0), over x views whose first
+    element is `shift` elements past a 16-byte boundary (head of 0..3 elements)."""
+    lens = []
+    for k in range(40):
+        lens += [chunk, chunk - 1, chunk + 1, 0, 0, 3 * chunk, 1, 2 * chunk + 7, 0, 5]
+    L = torch.tensor(lens, dtype=torch.int64)
+    off = synth.offsets_from_lengths(L) + 2
+    n = int(off[-1]) + 9
+    base = synth.uniform_pm1_f32(41, 0, n + shift)
+    xs = base[shift:]
+    b = hdc.tuning_bucket(n)
+    for acc in ("plain", "compensated"):
+        old = hdc.get_tuning(hdc.OP_SEGMENTED_REDUCE, hdc.F32, hdc.ACC[acc], b)
+        try:
+            hdc.set_tuning(hdc.OP_SEGMENTED_REDUCE, hdc.F32, hdc.ACC[acc], b, chunk=chunk, block=128, unroll=2,
+                           grid_mult=2)
+            r = hdc.segmented_reduce(base.to(gpu())[shift:], off.to(gpu()), FNS["horner"], acc)
+            check_segments(r, oracle.segmented(FNS["horner"], xs, off), f"tile edges {chunk} {shift} {acc}")
+        finally:
+            hdc.set_tuning(hdc.OP_SEGMENTED_REDUCE, hdc.F32, hdc.ACC[acc], b, **old)

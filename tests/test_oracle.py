@@ -564,3 +564,31 @@ def test_segmented_scan_brute_force():
         for i in range(lo, hi):
             acc += 3 * int(xi[i]) - 7
             assert ri[i] == acc
+
+
+def test_multithreaded_oracle_matches_single_thread():
+    """The multicore CPU baseline joins per-thread exact accumulators without rounding: its exact and
+    integer results are the single-thread oracle's bit for bit, and its maps are identical, for any
+    thread count (more threads than elements included)."""
+    horner = {"fn": "horner", "coef": synth.horner_coefficients(8)}
+    cases = [
+        ({"fn": "identity"}, synth.to_storage(synth.random_sign(11, 2, 5003) * torch.exp(4.0 * synth.normal_f64(11, 0, 5003)),
+                                              torch.float32), None),
+        (horner, synth.uniform_pm1_f32(12, 0, 40001), None),
+        ({"fn": "product"}, synth.to_storage(synth.normal_f64(13, 0, 7777), torch.float16),
+         synth.to_storage(synth.normal_f64(13, 1, 7777), torch.float16)),
+        ({"fn": "identity"}, synth.to_storage(synth.normal_f64(14, 0, 999), torch.bfloat16), None),
+        ({"fn": "affine", "a": 3, "b": -7}, synth.uniform_int(15, 0, 12345, bits=31), None),
+    ]
+    for spec, x, z in cases:
+        one = oracle.reduce(spec, x, z)
+        for threads in (1, 3, 8, 17, 64):
+            mt = oracle.reduce_mt(spec, x, z, threads=threads)
+            assert mt["exact"] == one["exact"] and mt["isum"] == one["isum"], (spec, threads)
+            assert math.isclose(mt["abs_sum"], one["abs_sum"], rel_tol=1e-12)
+            assert abs(mt["seq64"] - one["seq64"]) <= 1e-12 * one["abs_sum"]
+            if spec["fn"] != "product":
+                assert torch.equal(oracle.map_mt(spec, x, threads=threads), oracle.map(spec, x))
+    assert oracle.reduce_mt({"fn": "identity"}, torch.zeros(0), threads=4)["exact"] == 0.0
+    few = torch.tensor([1e30, 1.0, -1e30, 3.0, 2.0 ** -140], dtype=torch.float32)  # more threads than values
+    assert oracle.reduce_mt({"fn": "identity"}, few, threads=8)["exact"] == oracle.reduce({"fn": "identity"}, few)["exact"]
