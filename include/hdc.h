@@ -45,7 +45,17 @@
 extern "C" {
 #endif
 
-typedef enum hdc_status {
+/* The enums are 32-bit integers on both sides.  In C++ they get that fixed
+ * underlying type, so a caller's out-of-range value is still a value of the
+ * enum that the argument checks can reject (without it, merely loading such
+ * a value would be undefined). */
+#ifdef __cplusplus
+#define HDC_ENUM(name) enum name : int32_t
+#else
+#define HDC_ENUM(name) enum name
+#endif
+
+typedef HDC_ENUM(hdc_status) {
   HDC_OK = 0,
   HDC_ERR_INVALID_ARGUMENT = 1, /* null pointer, negative size, bad alignment */
   HDC_ERR_UNSUPPORTED = 2,      /* functor / dtype / accumulation not provided */
@@ -53,7 +63,7 @@ typedef enum hdc_status {
   HDC_ERR_HIP = 4               /* a HIP runtime call or kernel launch failed */
 } hdc_status;
 
-typedef enum hdc_dtype {
+typedef HDC_ENUM(hdc_dtype) {
   HDC_F32 = 0,  /* IEEE binary32 */
   HDC_F16 = 1,  /* IEEE binary16 */
   HDC_BF16 = 2, /* bfloat16 (upper half of binary32) */
@@ -62,7 +72,7 @@ typedef enum hdc_dtype {
   HDC_F64 = 5   /* declared for completeness; no operation accepts it yet */
 } hdc_dtype;
 
-typedef enum hdc_fn {
+typedef HDC_ENUM(hdc_fn) {
   HDC_FN_IDENTITY = 0, /* f(x) = x */
   HDC_FN_AFFINE = 1,   /* floats: f(x) = fma(a, x, b) in fp32 (one rounding);
                           int32: f(x) = ia*x + ib with two's-complement wrap
@@ -73,7 +83,7 @@ typedef enum hdc_fn {
   HDC_FN_PRODUCT = 3   /* dot-product term x[i]*z[i]; transform_reduce only */
 } hdc_fn;
 
-typedef enum hdc_accum {
+typedef HDC_ENUM(hdc_accum) {
   HDC_ACC_PLAIN = 0,       /* floats: fp32 partial sums; `out` is one float */
   HDC_ACC_COMPENSATED = 1, /* floats: fp32 TwoSum-compensated partials, fp64
                               final cross-block combine; `out` is one double */
@@ -92,7 +102,7 @@ typedef enum hdc_accum {
                               non-finite terms (inf * 0 is NaN). */
 } hdc_accum;
 
-typedef enum hdc_op {
+typedef HDC_ENUM(hdc_op) {
   HDC_OP_MAP = 0,
   HDC_OP_TRANSFORM_REDUCE = 1,
   HDC_OP_SEGMENTED_REDUCE = 2,

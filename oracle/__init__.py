@@ -23,7 +23,9 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# HDC_ORACLE_LIBRARY / HDC_ORACLE_MT_LIBRARY name other builds of the same
+# sources (the sanitized ones of build_sanitized()).
+LIB_PATH = os.environ.get("HDC_ORACLE_LIBRARY") or os.path.join(HERE, "liboracle.so")
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
           "-Wall", "-Wextra"]
 
@@ -44,7 +46,8 @@ class OrResult(ctypes.Structure):
                 ("abs_sum", ctypes.c_double), ("isum", ctypes.c_int64)]
 
 
-MT_LIB_PATH = os.path.join(HERE, "liboracle_mt.so")
+MT_LIB_PATH = os.environ.get("HDC_ORACLE_MT_LIBRARY") or os.path.join(HERE, "liboracle_mt.so")
+SAN_DIR = os.path.join(HERE, "_build")
 
 
 def build() -> str:
@@ -56,6 +59,22 @@ def build() -> str:
         subprocess.run(["gcc", *CFLAGS, "-o", tmp, src, "-lm", *extra], check=True)
         os.replace(tmp, out)
     return LIB_PATH
+
+
+def build_sanitized() -> tuple[str, str]:
+    """liboracle.so and liboracle_mt.so built by clang with AddressSanitizer and
+    UndefinedBehaviorSanitizer into oracle/_build/ (for the CPU sanitizer test)."""
+    os.makedirs(SAN_DIR, exist_ok=True)
+    flags = ["-O1", "-g", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+             "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+             "-shared-libsan"]
+    outs = []
+    for src, name, extra in (("oracle.c", "liboracle.so", []), ("oracle_mt.c", "liboracle_mt.so", ["-lpthread"])):
+        out = os.path.join(SAN_DIR, name)
+        subprocess.run(["/opt/rocm/llvm/bin/clang", *flags, "-o", out, os.path.join(HERE, src), "-lm", *extra],
+                       check=True)
+        outs.append(out)
+    return outs[0], outs[1]
 
 
 _lib = None

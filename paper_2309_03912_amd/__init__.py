@@ -19,7 +19,9 @@ import os
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libhdc.so")
+# HDC_LIBRARY names another build of the same sources (the sanitized host-only
+# build used by the CPU sanitizer test); there is no fallback either way.
+LIB_PATH = os.environ.get("HDC_LIBRARY") or os.path.join(HERE, "libhdc.so")
 # Tuning cache written by the autotuner for gfx950; loaded with the library
 # unless HDC_TUNE_CACHE names another one.
 TUNING_CACHE = os.path.join(HERE, "tuning_gfx950.txt")

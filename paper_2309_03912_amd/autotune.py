@@ -184,12 +184,35 @@ def candidates(op, quick=False):
     seg = [dict(chunk=c, small_seg=s, seg_per_wave=w)
            for c, s, w in itertools.product([2048, 4096, 8192] if quick else [1024, 2048, 4096, 8192, 16384],
                                             [64, 128, 256, 512], [2, 4, 8, 16] if quick else [1, 2, 4, 8, 16, 32, 64])]
-    # three stages: the schedule (tiled or planned), the geometry at the default split, then the split
-    # (tile length for the tiled schedule; piece length and small-segment packing for the planned one)
-    return [dict(passes=p) for p in (1, 2)], base, seg
+    # per schedule (tiled, planned): the geometry at the default split, then the split (tile length for
+    # the tiled schedule; piece length and small-segment packing for the planned one)
+    return base, seg
 
 
 def tune_case(case: Case, quick=False, reps=5, rounds=3, log=print):
+    op, dt, acc, b = case.key()
+    if op == OP_SEGMENTED_REDUCE:
+        # each schedule tuned on its own, then the two winners timed against each other
+        start = get_tuning(op, dt, acc, b)
+        wins = []
+        for passes in (1, 2):
+            set_tuning(op, dt, acc, b, **dict(start, passes=passes))
+            wins.append(_tune_stages(case, quick, reps, rounds, log))
+        times = {i: [] for i in range(2)}
+        for _ in range(2 * rounds):
+            for i, w in enumerate(wins):
+                set_tuning(op, dt, acc, b, **w)
+                times[i].append(_time(case.run, reps))
+        best = wins[min(times, key=lambda i: statistics.median(times[i]))]
+        set_tuning(op, dt, acc, b, **best)
+        log(json.dumps({"class": case.key(), "schedules": [
+            {"passes": w["passes"], "ms": round(statistics.median(times[i]), 5)} for i, w in enumerate(wins)],
+            "best": best}))
+        return best
+    return _tune_stages(case, quick, reps, rounds, log)
+
+
+def _tune_stages(case: Case, quick, reps, rounds, log):
     op, dt, acc, b = case.key()
     cands = candidates(op, quick)
     stages = list(cands) if isinstance(cands, tuple) else [cands]

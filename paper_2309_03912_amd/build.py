@@ -92,6 +92,55 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     return LIB_PATH
 
 
+SAN_DIR = os.path.join(BUILD_DIR, "sanitized")
+CLANGXX = "/opt/rocm/llvm/bin/clang++"
+
+
+def asan_runtime() -> str:
+    """The clang AddressSanitizer runtime that a sanitized build needs preloaded."""
+    import glob
+    hits = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not hits:
+        raise RuntimeError("no clang AddressSanitizer runtime found under /opt/rocm/llvm")
+    return hits[-1]
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """Every translation unit built with AddressSanitizer and
+    UndefinedBehaviorSanitizer on its host side (the device code is compiled as
+    usual), linked as _build/sanitized/libhdc.so: for CPU-only tests of the
+    argument checks, the workspace and tuning logic and the host backend."""
+    os.makedirs(SAN_DIR, exist_ok=True)
+    host_flags = ["--offload-arch=gfx950", "-std=c++20", "-O1", "-g", "-fPIC",
+                  "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                  "-Wno-unused-command-line-argument",
+                  "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+    def one(unit):
+        src, obj, defs = unit
+        out = os.path.join(SAN_DIR, obj + ".o")
+        cmd = [HIPCC, *host_flags, *defs, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c", "-o", out,
+               os.path.join(CSRC, src)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        proc = subprocess.run(cmd, capture_output=True, text=True)
+        if proc.returncode != 0:
+            raise RuntimeError(f"sanitized host compile failed on {src}:\n" + _filter(proc.stderr))
+        return out
+
+    with ThreadPoolExecutor(max_workers=min(len(UNITS), os.cpu_count() or 4)) as ex:
+        objs = list(ex.map(one, UNITS))
+    lib = os.path.join(SAN_DIR, "libhdc.so")
+    # host link of the objects (no .hip source on this line)
+    link = [CLANGXX, "-shared", "-fsanitize=address,undefined", "-shared-libsan", "-o", lib, *objs,
+            "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"]
+    proc = subprocess.run(link, capture_output=True, text=True)
+    if proc.returncode != 0:
+        raise RuntimeError("sanitized link failed:\n" + proc.stderr)
+    return lib
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
     print(build_probe(verbose=True))

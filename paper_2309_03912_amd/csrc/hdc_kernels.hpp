@@ -62,7 +62,9 @@ __host__ __device__ __forceinline__ void fold_elem(Acc& a, const F& f, elem_t<S>
 // Horner runs coefficient-outermost so that each coefficient (a uniform
 // value) feeds N independent fma chains; each element still sees exactly the
 // fma sequence of Horner::operator(), so results are bit-identical to it.
-template <class F, int N>
+// kChain selects the straight chain for any batch size (kernels whose other
+// scalar state leaves no room for the guards' saved conditions).
+template <class F, int N, bool kChain = (N < 8)>
 __host__ __device__ __forceinline__ void eval_batch(const F& f, float (&t)[N]) {
   if constexpr (std::is_same_v<F, Horner>) {
     // Every coefficient index is a constant in both forms below, so the
@@ -71,7 +73,7 @@ __host__ __device__ __forceinline__ void eval_batch(const F& f, float (&t)[N]) {
     // guard per step; small batches (where the guards' saved conditions would
     // crowd the scalar registers) enter a straight chain at their degree.
     float acc[N];
-    if constexpr (N >= 8) {
+    if constexpr (!kChain) {
       float top = f.c[0];
 #pragma unroll
       for (int k = 1; k <= kMaxDegree; ++k) top = k == f.degree ? f.c[k] : top;

@@ -112,25 +112,45 @@ static __global__ __launch_bounds__(1024) void seg_count_scan_kernel(int64_t nbl
 }
 
 // Plan pass 3: every segment writes its entries at its block's base plus its
-// prefix within the block.
+// prefix within the block.  A segment writes its first kOwnPieces full-piece
+// entries itself; the block writes the rest of every longer one together.
+constexpr int64_t kOwnPieces = 16;
+
 static __global__ __launch_bounds__(kPlanBlock) void seg_write_kernel(const int64_t* __restrict__ off, int64_t S,
                                                                       SegPlan p) {
   __shared__ SegCounters lds[kMaxWaves];
+  __shared__ int nbig;
+  __shared__ int64_t big_j[kPlanBlock], big_f0[kPlanBlock], big_n[kPlanBlock];
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const SegShape sh = seg_shape(off, S, p, j);
   SegCounters total;
   const SegCounters pre = SegCounters::merge(p.block_tot[blockIdx.x],
                                              block_exclusive_scan_acc(sh.want, lds, &total));
-  if (!sh.big) return;
-  if (sh.pieces > 1) {
-    const int64_t slot0 = pre.partials, li = pre.longs;
-    p.long_base[j] = slot0 + sh.pieces <= p.cap_partials ? (int32_t)slot0 : -1;
-    if (li < p.cap_part) p.long_list[li] = (int32_t)j;
+  if (threadIdx.x == 0) nbig = 0;
+  __syncthreads();
+  if (sh.big) {
+    if (sh.pieces > 1) {
+      const int64_t slot0 = pre.partials, li = pre.longs;
+      p.long_base[j] = slot0 + sh.pieces <= p.cap_partials ? (int32_t)slot0 : -1;
+      if (li < p.cap_part) p.long_list[li] = (int32_t)j;
+    }
+    const int64_t f0 = pre.full;
+    const int64_t own = sh.nfull < kOwnPieces ? sh.nfull : kOwnPieces;
+    for (int64_t k = 0; k < own; ++k)
+      if (f0 + k < p.cap_full) p.full_list[f0 + k] = SegPiece{(int32_t)j, (int32_t)k};
+    if (sh.nfull > kOwnPieces) {
+      const int q = atomicAdd(&nbig, 1);
+      big_j[q] = j;
+      big_f0[q] = f0;
+      big_n[q] = sh.nfull;
+    }
+    if (sh.want.part && (int64_t)pre.part < p.cap_part)
+      p.part_list[pre.part] = SegPiece{(int32_t)j, (int32_t)sh.nfull};
   }
-  const int64_t f0 = pre.full;
-  for (int64_t k = 0; k < sh.nfull; ++k)
-    if (f0 + k < p.cap_full) p.full_list[f0 + k] = SegPiece{(int32_t)j, (int32_t)k};
-  if (sh.want.part && (int64_t)pre.part < p.cap_part) p.part_list[pre.part] = SegPiece{(int32_t)j, (int32_t)sh.nfull};
+  __syncthreads();
+  for (int q = 0; q < nbig; ++q)  // every entry's content is fixed, whatever q a segment drew
+    for (int64_t k = kOwnPieces + threadIdx.x; k < big_n[q]; k += blockDim.x)
+      if (big_f0[q] + k < p.cap_full) p.full_list[big_f0[q] + k] = SegPiece{(int32_t)big_j[q], (int32_t)k};
 }
 
 // True when the plan's lists exceed the workspace's capacity.  The plan then
@@ -464,48 +484,53 @@ struct TileWave {
   const F& f;
   const elem_t<S>* x;  // x + off[0]
   const int64_t* off;
-  int64_t S_;
-  const TileGeom& g;
+  int64_t lo;          // off[0]
+  int32_t S_;
   SegTiles st;
   void* out;
   int lane;
-  int64_t tile;
-  // wavefront-uniform state of the current segment
-  int64_t j;        // the segment holding the next position
-  int64_t nb;       // its end, off[j + 1] - off[0]
+  int32_t tile;
+  int64_t base;     // position (relative to off[0]) of the tile's first element
+  int32_t len;      // elements of the tile
+  // wavefront-uniform state of the current segment; positions are relative to `base`
+  int32_t j;        // the segment holding the next position
+  int32_t nb;       // its end (off[j + 1] - off[0] - base), clamped to len + 1
   bool started;     // it starts inside this tile
-  int64_t bbase;    // offsets[bbase + l] are in lane l of `bnd`
+  int32_t bbase;    // offsets[bbase + l] are in lane l of `bnd`
   int64_t bnd;      // a batch of 64 offsets (relative to off[0]); past off[S]: INT64_MAX
   Acc acc;
 
-  // Find the segment holding position p (relative to off[0]): the last j with
-  // off[j] - off[0] <= p.  Rounds of 64 evenly spaced probes narrow the range
-  // to at most 64 offsets, whose final round is kept as the boundary batch.
-  __device__ void locate(int64_t p) {
-    int64_t lo = 0, len = S_ + 1;  // off[lo] - off[0] <= p; the answer is in [lo, lo + len)
-    while (len > 64) {
-      const int64_t step = (len + 63) / 64;
-      const int64_t idx = lo + (int64_t)lane * step;
-      const bool le = idx < lo + len && off[idx] - g.lo <= p;
-      const int cnt = __builtin_popcountll(__builtin_amdgcn_ballot_w64(le));  // a prefix of the lanes
-      const int64_t nlo = lo + (int64_t)(cnt - 1) * step;
-      len = lo + len - nlo < step ? lo + len - nlo : step;
-      lo = nlo;
-    }
-    load_batch(lo);
-    const int cnt = __builtin_popcountll(__builtin_amdgcn_ballot_w64(lane < len && bnd <= p));
-    j = lo + cnt - 1;
+  __device__ void load_batch(int32_t b) {
+    bbase = b;
+    const int64_t i = (int64_t)b + lane;
+    bnd = i <= S_ ? off[i] - lo : INT64_MAX;
+  }
+  // off[i] - off[0] - base, clamped to len + 1, from the batch (reloaded when passed)
+  __device__ int32_t bound(int32_t i) {
+    if (i - bbase >= 64) load_batch(i);
+    const int64_t v = read_lane(bnd, i - bbase) - base;
+    return v <= len ? (int32_t)v : len + 1;
   }
 
-  __device__ void load_batch(int64_t base) {
-    bbase = base;
-    const int64_t i = base + lane;
-    bnd = i <= S_ ? off[i] - g.lo : INT64_MAX;
-  }
-  // off[i] - off[0] for i in [bbase, ...), from the batch (reloaded when passed)
-  __device__ int64_t bound(int64_t i) {
-    if (i - bbase >= 64) load_batch(i);
-    return read_lane(bnd, (int)(i - bbase));
+  // Find the segment holding tile position 0: the last j with
+  // off[j] - off[0] <= base.  Rounds of 64 evenly spaced probes narrow the
+  // range to at most 64 offsets, whose final round is kept as the batch.
+  __device__ void locate() {
+    int64_t a = 0, n = (int64_t)S_ + 1;  // off[a] - off[0] <= base; the answer is in [a, a + n)
+    while (n > 64) {
+      const int64_t step = (n + 63) / 64;
+      const int64_t idx = a + (int64_t)lane * step;
+      const bool le = idx < a + n && off[idx] - lo <= base;
+      const int cnt = __builtin_popcountll(__builtin_amdgcn_ballot_w64(le));  // a prefix of the lanes
+      const int64_t na = a + (int64_t)(cnt - 1) * step;
+      n = a + n - na < step ? a + n - na : step;
+      a = na;
+    }
+    load_batch((int32_t)a);
+    const int cnt = __builtin_popcountll(__builtin_amdgcn_ballot_w64(lane < n && bnd <= base));
+    j = (int32_t)a + cnt - 1;
+    started = read_lane(bnd, j - bbase) >= base;
+    nb = bound(j + 1);
   }
 
   // Store the fold of a segment part that ends inside this tile.
@@ -519,7 +544,7 @@ struct TileWave {
   }
   // Leave segment j at its end nb: the next non-empty segment starts there.
   __device__ void advance() {
-    const int64_t b = nb;
+    const int32_t b = nb;
     do {
       ++j;
       nb = bound(j + 1);
@@ -527,28 +552,28 @@ struct TileWave {
     started = true;
   }
 
-  // Add a step's terms.  Term k sits at position ps + rel(k) and exists iff
-  // ok(k); every position of the step lies in [ps, pe), pe - ps < 2^31.
-  template <class Rel, class Ok>
-  __device__ void step(const Term (&t)[K], Rel rel, Ok ok, int64_t ps, int64_t pe) {
+  // Add a step's terms.  Term k sits at tile position ps + rel(k) and exists
+  // iff kFull or ok(k); every position of the step lies in [ps, pe).
+  template <bool kFull, class Rel, class Ok>
+  __device__ void step(const Term (&t)[K], Rel rel, Ok ok, int32_t ps, int32_t pe) {
     if (nb >= pe) {  // no boundary inside the step (uniform)
 #pragma unroll
       for (int k = 0; k < K; ++k)
-        if (ok(k)) acc.add(t[k]);
+        if (kFull || ok(k)) acc.add(t[k]);
       return;
     }
-    int prev = 0;  // terms before ps + prev are already folded
+    int32_t prev = 0;  // terms before ps + prev are already folded
     while (nb < pe) {
-      const int end = (int)(nb - ps);
+      const int32_t end = nb - ps;
 #pragma unroll
-      for (int k = 0; k < K; ++k) acc.add(ok(k) && rel(k) >= prev && rel(k) < end ? t[k] : Term{});
+      for (int k = 0; k < K; ++k) acc.add((kFull || ok(k)) && rel(k) >= prev && rel(k) < end ? t[k] : Term{});
       finish(wave_reduce(acc, MergeOp<Acc>{}));
       acc = Acc::zero();
       prev = end;
       advance();
     }
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc.add(ok(k) && rel(k) >= prev ? t[k] : Term{});
+    for (int k = 0; k < K; ++k) acc.add((kFull || ok(k)) && rel(k) >= prev ? t[k] : Term{});
   }
 
   __device__ void terms(const elem_t<S> (&v)[K], Term (&t)[K]) {
@@ -559,51 +584,50 @@ struct TileWave {
       float w[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) w[k] = S::widen(v[k]);
-      eval_batch(f, w);
+      eval_batch<F, K, true>(f, w);
 #pragma unroll
       for (int k = 0; k < K; ++k) t[k] = w[k];
     }
   }
 
-  // A step of single elements: lane l takes position p0 + l if below p1.
-  __device__ void scalar_step(int64_t p0, int64_t p1) {
+  // A step of single elements: lane l takes tile position p0 + l if below p1.
+  __device__ void scalar_step(int32_t p0, int32_t p1) {
     const bool mine = p0 + lane < p1;
     elem_t<S> v[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = k == 0 && mine ? x[p0 + lane] : elem_t<S>{};
+    for (int k = 0; k < K; ++k) v[k] = k == 0 && mine ? x[base + p0 + lane] : elem_t<S>{};
     Term t[K];
     terms(v, t);
-    step(t, [&](int) { return lane; }, [&](int k) { return k == 0 && mine; }, p0, p1);
+    step<false>(t, [&](int) { return lane; }, [&](int k) { return k == 0 && mine; }, p0, p1);
   }
 
-  __device__ void run() {
-    const int64_t vb = tile * st.tile_vecs;
+  __device__ void run(const TileGeom& g) {
+    const int64_t vb = (int64_t)tile * st.tile_vecs;
     const int64_t ve = vb + st.tile_vecs < g.nvec ? vb + st.tile_vecs : g.nvec;
     const bool first_tile = tile == 0, last_tile = tile == g.ntiles - 1;
-    const int64_t ps0 = first_tile ? 0 : g.head + vb * KV;
-    const int64_t pe0 = last_tile ? g.n : g.head + ve * KV;
-    const elem_t<S>* xv = x + g.head;
+    base = first_tile ? 0 : g.head + vb * KV;
+    const int64_t end = last_tile ? g.n : g.head + ve * KV;
+    len = (int32_t)(end - base);
+    const int32_t vpos = (int32_t)(g.head + vb * KV - base);  // tile position of vector vb
+    const elem_t<S>* xv = x + g.head + vb * KV;             // vector vb
+    const int32_t nvt = (int32_t)(ve - vb);                 // vectors of the tile
     Vec<S> a[U];
-    auto issue = [&](int64_t v0) {
+    auto issue = [&](int32_t v0) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int64_t vi = v0 + u * 64 + lane;
-        a[u] = vi < ve ? load16<S>(xv + vi * KV) : Vec<S>{};
+        const int32_t vi = v0 + u * 64 + lane;
+        a[u] = vi < nvt ? load16<S>(xv + (int64_t)vi * KV) : Vec<S>{};
       }
     };
     // The first step's loads go out before the search for the segment
-    // holding ps0 (which needs three dependent rounds of offsets).
-    if (vb < ve) issue(vb);
-    locate(ps0);
-    started = read_lane(bnd, (int)(j - bbase)) >= ps0;
-    nb = bound(j + 1);
+    // holding the tile's first element (three dependent rounds of offsets).
+    if (nvt > 0) issue(0);
+    locate();
     acc = Acc::zero();
 
-    if (first_tile && g.head > 0) scalar_step(0, g.head);
-    for (int64_t v0 = vb; v0 < ve; v0 += 64 * U) {
-      if (v0 != vb) issue(v0);
-      const bool full = v0 + 64 * U <= ve;
-      const int nv = full ? 64 * U : (int)(ve - v0);  // vectors of this step
+    if (first_tile && g.head > 0) scalar_step(0, (int32_t)g.head);
+    for (int32_t v0 = 0; v0 < nvt; v0 += 64 * U) {
+      if (v0 != 0) issue(v0);
       elem_t<S> v[K];
 #pragma unroll
       for (int u = 0; u < U; ++u)
@@ -612,14 +636,20 @@ struct TileWave {
       Term t[K];
       terms(v, t);
       // term (u, e) is element e of vector v0 + 64 u + lane
-      step(t, [&](int k) { return ((k / KV) * 64 + lane) * KV + k % KV; },
-           [&](int k) { return full || (k / KV) * 64 + lane < nv; }, g.head + v0 * KV, g.head + (v0 + nv) * KV);
+      auto rel = [&](int k) { return ((k / KV) * 64 + lane) * KV + k % KV; };
+      const int32_t ps = vpos + v0 * KV;
+      if (v0 + 64 * U <= nvt) {
+        step<true>(t, rel, [](int) { return true; }, ps, ps + 64 * U * KV);
+      } else {
+        const int32_t nv = nvt - v0;
+        step<false>(t, rel, [&](int k) { return (k / KV) * 64 + lane < nv; }, ps, ps + nv * KV);
+      }
     }
-    if (last_tile && g.tail_start < g.n) scalar_step(g.tail_start, g.n);
+    if (last_tile && g.tail_start < g.n) scalar_step((int32_t)(g.tail_start - base), len);
 
     // The segment open at the tile's end: it ends exactly there, or runs on.
     const Acc total = wave_reduce(acc, MergeOp<Acc>{});
-    if (nb == pe0) {
+    if (nb == len) {
       finish(total);
     } else if (lane == 0) {
       if (started)
@@ -649,8 +679,8 @@ __global__ __launch_bounds__(1024) void seg_tiles_kernel(F f, const elem_t<S>* _
     return;
   }
   for (int64_t t = w; t < g.ntiles; t += W) {
-    TileWave<F, S, Acc, U> tw{f, x + g.lo, off, S_, g, st, out, lane, t};
-    tw.run();
+    TileWave<F, S, Acc, U> tw{f, x + g.lo, off, g.lo, (int32_t)S_, st, out, lane, (int32_t)t};
+    tw.run(g);
   }
 }
 

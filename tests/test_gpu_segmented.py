@@ -239,3 +239,19 @@ def test_segmented_boundaries_on_and_around_tile_edges(chunk, shift):
             check_segments(r, oracle.segmented(FNS["horner"], xs, off), f"tile edges {chunk} {shift} {acc}")
         finally:
             hdc.set_tuning(hdc.OP_SEGMENTED_REDUCE, hdc.F32, hdc.ACC[acc], b, **old)
+
+
+def test_segmented_very_long_segments():
+    """Segments of 2^24 + 3 and 2^22 elements among short and empty ones: the tiled schedule folds
+    their many tile parts with a whole wavefront, the planned one writes their thousands of piece
+    entries with a whole plan block."""
+    L = torch.tensor([5, (1 << 24) + 3, 0, 7, 1 << 22, 1, 0, 3000], dtype=torch.int64)
+    off = synth.offsets_from_lengths(L)
+    x = synth.uniform_pm1_f32(43, 0, int(off[-1]))
+    g, og = x.to(gpu()), off.to(gpu())
+    for acc in ("plain", "compensated"):
+        r = hdc.segmented_reduce(g, og, FNS["horner"], acc)
+        check_segments(r, oracle.segmented(FNS["horner"], x, off), f"long segments {acc}")
+    xi = synth.uniform_int(44, 0, int(off[-1]))
+    r = hdc.segmented_reduce(xi.to(gpu()), og, {"fn": "affine", "a": 3, "b": -7}, "exact_int")
+    assert np.array_equal(r.cpu().numpy(), oracle.segmented({"fn": "affine", "a": 3, "b": -7}, xi, off)["isum"])
