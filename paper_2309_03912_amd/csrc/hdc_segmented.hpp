@@ -474,6 +474,40 @@ __host__ __device__ __forceinline__ int64_t tile_of(const TileGeom& g, int64_t t
   return t < g.ntiles - 1 ? t : g.ntiles - 1;
 }
 
+// Search for the segment holding position p (relative to off[0]), one round
+// at a time so that the rounds can overlap other work: a round probes 64
+// evenly spaced offsets and narrows the range to one gap between probes;
+// the final round loads the (at most) 64 offsets of the range, which become
+// the boundary batch.  For 100,000 segments: three rounds.
+struct SegFinder {
+  int64_t p;
+  int32_t a, n;     // off[a] - off[0] <= p; the answer is in [a, a + n)
+  int32_t step;     // spacing of the round in flight (1: the final round)
+  int64_t probe;    // this lane's probe of the round in flight, minus off[0]; INT64_MAX if none
+
+  __device__ void issue(const int64_t* off, int64_t lo, int32_t S, int lane) {
+    step = n > 64 ? (n + 63) / 64 : 1;
+    const int64_t idx = (int64_t)a + (int64_t)lane * step;
+    const bool ok = step == 1 ? idx <= S : idx < (int64_t)a + n;
+    probe = ok ? off[idx] - lo : INT64_MAX;
+  }
+  __device__ void start(const int64_t* off, int64_t lo, int32_t S, int64_t p_, int lane) {
+    p = p_;
+    a = 0;
+    n = S + 1;
+    issue(off, lo, S, lane);
+  }
+  __device__ bool final_round() const { return step == 1; }
+  // Consume a non-final round and issue the next one.
+  __device__ void next(const int64_t* off, int64_t lo, int32_t S, int lane) {
+    const int cnt = __builtin_popcountll(__builtin_amdgcn_ballot_w64(probe <= p));  // a prefix of the lanes
+    const int32_t na = a + (cnt - 1) * step;
+    n = a + n - na < step ? a + n - na : step;
+    a = na;
+    issue(off, lo, S, lane);
+  }
+};
+
 template <class F, class S, class Acc, int U>
 struct TileWave {
   static constexpr int KV = S::kVec;
@@ -512,23 +546,14 @@ struct TileWave {
     return v <= len ? (int32_t)v : len + 1;
   }
 
-  // Find the segment holding tile position 0: the last j with
-  // off[j] - off[0] <= base.  Rounds of 64 evenly spaced probes narrow the
-  // range to at most 64 offsets, whose final round is kept as the batch.
-  __device__ void locate() {
-    int64_t a = 0, n = (int64_t)S_ + 1;  // off[a] - off[0] <= base; the answer is in [a, a + n)
-    while (n > 64) {
-      const int64_t step = (n + 63) / 64;
-      const int64_t idx = a + (int64_t)lane * step;
-      const bool le = idx < a + n && off[idx] - lo <= base;
-      const int cnt = __builtin_popcountll(__builtin_amdgcn_ballot_w64(le));  // a prefix of the lanes
-      const int64_t na = a + (int64_t)(cnt - 1) * step;
-      n = a + n - na < step ? a + n - na : step;
-      a = na;
-    }
-    load_batch((int32_t)a);
-    const int cnt = __builtin_popcountll(__builtin_amdgcn_ballot_w64(lane < n && bnd <= base));
-    j = (int32_t)a + cnt - 1;
+  // The segment holding tile position 0 (the last j with off[j] - off[0] <=
+  // base), from a finder started for `base`: its remaining rounds run here.
+  __device__ void locate(SegFinder& fd) {
+    while (!fd.final_round()) fd.next(off, lo, S_, lane);
+    bbase = fd.a;
+    bnd = fd.probe;
+    const int cnt = __builtin_popcountll(__builtin_amdgcn_ballot_w64(lane < fd.n && bnd <= base));
+    j = fd.a + cnt - 1;
     started = read_lane(bnd, j - bbase) >= base;
     nb = bound(j + 1);
   }
@@ -601,7 +626,15 @@ struct TileWave {
     step<false>(t, [&](int) { return lane; }, [&](int k) { return k == 0 && mine; }, p0, p1);
   }
 
-  __device__ void run(const TileGeom& g) {
+  // Tile position 0 of tile t, relative to off[0].
+  __device__ static int64_t tile_base(const TileGeom& g, int64_t tile_vecs, int64_t t) {
+    return t == 0 ? 0 : g.head + t * tile_vecs * KV;
+  }
+
+  // `fd` holds a search started for this tile (have == true) or nothing; on
+  // return it holds one started for tile `next` (next >= 0), whose rounds ran
+  // between this tile's steps.
+  __device__ void run(const TileGeom& g, SegFinder& fd, bool have, int64_t next) {
     const int64_t vb = (int64_t)tile * st.tile_vecs;
     const int64_t ve = vb + st.tile_vecs < g.nvec ? vb + st.tile_vecs : g.nvec;
     const bool first_tile = tile == 0, last_tile = tile == g.ntiles - 1;
@@ -620,9 +653,13 @@ struct TileWave {
       }
     };
     // The first step's loads go out before the search for the segment
-    // holding the tile's first element (three dependent rounds of offsets).
+    // holding the tile's first element finishes (three dependent rounds of
+    // offsets, most of them already run during the previous tile).
     if (nvt > 0) issue(0);
-    locate();
+    if (!have) fd.start(off, lo, S_, base, lane);
+    locate(fd);
+    if (next >= 0) fd.start(off, lo, S_, tile_base(g, st.tile_vecs, next), lane);
+    bool searching = next >= 0;
     acc = Acc::zero();
 
     if (first_tile && g.head > 0) scalar_step(0, (int32_t)g.head);
@@ -643,6 +680,12 @@ struct TileWave {
       } else {
         const int32_t nv = nvt - v0;
         step<false>(t, rel, [&](int k) { return (k / KV) * 64 + lane < nv; }, ps, ps + nv * KV);
+      }
+      if (searching) {  // one round of the next tile's search per step
+        if (fd.final_round())
+          searching = false;
+        else
+          fd.next(off, lo, S_, lane);
       }
     }
     if (last_tile && g.tail_start < g.n) scalar_step((int32_t)(g.tail_start - base), len);
@@ -678,9 +721,13 @@ __global__ __launch_bounds__(1024) void seg_tiles_kernel(F f, const elem_t<S>* _
     }
     return;
   }
+  SegFinder fd{};
+  bool have = false;
   for (int64_t t = w; t < g.ntiles; t += W) {
     TileWave<F, S, Acc, U> tw{f, x + g.lo, off, g.lo, (int32_t)S_, st, out, lane, (int32_t)t};
-    tw.run(g);
+    const int64_t next = t + W < g.ntiles ? t + W : -1;
+    tw.run(g, fd, have, next);
+    have = next >= 0;
   }
 }
 

@@ -255,3 +255,40 @@ def test_segmented_very_long_segments():
     xi = synth.uniform_int(44, 0, int(off[-1]))
     r = hdc.segmented_reduce(xi.to(gpu()), og, {"fn": "affine", "a": 3, "b": -7}, "exact_int")
     assert np.array_equal(r.cpu().numpy(), oracle.segmented({"fn": "affine", "a": 3, "b": -7}, xi, off)["isum"])
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_segmented_random_layouts_and_tunings(case):
+    """Seeded random segment layouts of different shapes (geometric lengths, bursts of empty segments,
+    a few huge segments among tiny ones, lengths at tile multiples) under a random valid tuning,
+    against the oracle segment by segment."""
+    rng = np.random.default_rng(230903990 + case)
+    kind = case % 3
+    if kind == 0:
+        L = rng.geometric(1.0 / rng.integers(2, 3000), size=int(rng.integers(50, 3000))) - 1
+    elif kind == 1:
+        L = rng.integers(0, 70, size=4000)
+        L[rng.random(L.size) < 0.5] = 0  # bursts of empty segments
+        L[rng.integers(0, L.size, 3)] = rng.integers(100000, 400000, 3)
+    else:
+        L = rng.choice([0, 1, 1023, 1024, 1025, 2048, 4096, 8191, 8192, 16384], size=800)
+    L = torch.tensor(L, dtype=torch.int64)
+    off = synth.offsets_from_lengths(L) + int(rng.integers(0, 5))
+    n = int(off[-1]) + int(rng.integers(0, 9))
+    shift = int(rng.integers(0, 4))
+    base = synth.uniform_pm1_f32(230903991 + case, 0, n + shift)
+    xs = base[shift:]
+    g, og = base.to(gpu())[shift:], off.to(gpu())
+    b = hdc.tuning_bucket(n)
+    acc = ("plain", "compensated")[case % 2]
+    a = hdc.ACC[acc]
+    old = hdc.get_tuning(hdc.OP_SEGMENTED_REDUCE, hdc.F32, a, b)
+    try:
+        hdc.set_tuning(hdc.OP_SEGMENTED_REDUCE, hdc.F32, a, b, block=int(rng.choice([64, 128, 256, 512])),
+                       unroll=int(rng.choice([1, 2, 4])), grid_mult=int(rng.choice([1, 4, 16, 64])),
+                       chunk=int(rng.choice([1024, 2048, 4096, 8192])), small_seg=int(rng.choice([1, 64, 256])),
+                       seg_per_wave=int(rng.choice([1, 4, 16])))
+        r = hdc.segmented_reduce(g, og, FNS["horner"], acc)
+        check_segments(r, oracle.segmented(FNS["horner"], xs, off), f"random layout {case} {acc}")
+    finally:
+        hdc.set_tuning(hdc.OP_SEGMENTED_REDUCE, hdc.F32, a, b, **old)
