@@ -73,20 +73,33 @@ def gbps(nbytes, ms):
     return nbytes / (ms * 1e-3) / 1e9
 
 
-def ev_time(torch, fn, reps=20, warm=3):
+def ev_time(torch, fn, reps=20, warm=3, groups=5, warm_s=0.25):
     """Mean ms per call of `fn` over `reps` calls issued back to back, from two HIP events on the
-    current stream around the whole run: the time each call adds to a stream of work, with no idle
-    GPU between calls (a lone call on an idle GPU also waits for its own launch from the host)."""
+    current stream around each group of calls (the time each call adds to a stream of work, with no
+    idle GPU between calls; a lone call on an idle GPU also waits for its own launch from the host).
+    Before timing, `fn` runs `warm` times and then for at least `warm_s` seconds: an idle GPU runs
+    its first fraction of a second at lower clocks, and a short kernel timed then reads up to ~20%
+    slow.  Returns the median over `groups` groups."""
     for _ in range(warm):
         fn()
-    s = torch.cuda.Event(enable_timing=True)
-    e = torch.cuda.Event(enable_timing=True)
-    s.record()
-    for _ in range(reps):
-        fn()
-    e.record()
-    e.synchronize()
-    return s.elapsed_time(e) / reps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < warm_s:
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+    ts = []
+    for _ in range(groups):
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            fn()
+        e.record()
+        e.synchronize()
+        ts.append(s.elapsed_time(e) / reps)
+    ts.sort()
+    return ts[len(ts) // 2]
 
 
 def err_fields(got, ref):

@@ -202,16 +202,22 @@ hdc_status hdc_transform_reduce_noalloc(const hdc_functor* f, hdc_dtype dt,
  *   (a precondition, not checked per call: checking it would need a device
  *   round trip; hdc_validate_offsets checks it synchronously).
  *   out: S floats (PLAIN), doubles (COMPENSATED) or int64 (EXACT_INT).
- *   Empty segments give 0.  The whole batch is one plan pass, one
- *   persistent pass and one combine pass, with no host synchronisation.
+ *   Empty segments give 0.  No host synchronisation (with a workspace).
+ *   Two schedules, chosen by the tuning's `passes`: tiled (1) streams fixed
+ *   tiles of the element range and folds the segments that span tiles in a
+ *   second launch; planned (2) builds work lists in three small launches,
+ *   runs one persistent pass over them and a combine launch.  Both give
+ *   reproducible bits for a fixed tuning.
  *   IDENTITY, AFFINE, HORNER as for transform_reduce (no PRODUCT).
  *   workspace: at least hdc_workspace_size(HDC_OP_SEGMENTED_REDUCE, dt, acc,
  *   total, S) bytes for a total >= offsets[S]; its size sets the capacity
  *   of the work lists.  If the segments need more than ws_bytes holds
  *   (offsets[S] above the total it was sized for), the call still returns
  *   the correct sums, folding every segment whole with one wavefront
- *   (slower, and the last bits of a floating-point sum may differ).  The
- *   size bucket of the tuning is that of the largest total ws_bytes serves.
+ *   (slower, and the last bits of a floating-point sum may differ); the
+ *   tiled schedule does the same when the workspace holds fewer tile slots
+ *   than the range has tiles.  The size bucket of the tuning is that of the
+ *   largest total ws_bytes serves.
  *   NULL: the library's buffer, sized from offsets[S], which the call then
  *   reads from the device (a synchronous 8-byte copy on `stream`; refused
  *   with HDC_ERR_WORKSPACE under graph capture).

@@ -644,18 +644,22 @@ struct TileWave {
     const int32_t vpos = (int32_t)(g.head + vb * KV - base);  // tile position of vector vb
     const elem_t<S>* xv = x + g.head + vb * KV;             // vector vb
     const int32_t nvt = (int32_t)(ve - vb);                 // vectors of the tile
-    Vec<S> a[U];
-    auto issue = [&](int32_t v0) {
+    // Two steps of loads in flight: step s + 1's loads go out before step s
+    // is folded.
+    Vec<S> a[U], nx[U];
+    // Lanes past the tile's last vector load that vector again (the partial
+    // step masks their terms out), so no register is written before its load.
+    auto issue = [&](Vec<S>(&d)[U], int32_t v0) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int32_t vi = v0 + u * 64 + lane;
-        a[u] = vi < nvt ? load16<S>(xv + (int64_t)vi * KV) : Vec<S>{};
+        d[u] = load16<S>(xv + (int64_t)(vi < nvt ? vi : nvt - 1) * KV);
       }
     };
     // The first step's loads go out before the search for the segment
     // holding the tile's first element finishes (three dependent rounds of
     // offsets, most of them already run during the previous tile).
-    if (nvt > 0) issue(0);
+    if (nvt > 0) issue(a, 0);
     if (!have) fd.start(off, lo, S_, base, lane);
     locate(fd);
     if (next >= 0) fd.start(off, lo, S_, tile_base(g, st.tile_vecs, next), lane);
@@ -663,13 +667,13 @@ struct TileWave {
     acc = Acc::zero();
 
     if (first_tile && g.head > 0) scalar_step(0, (int32_t)g.head);
-    for (int32_t v0 = 0; v0 < nvt; v0 += 64 * U) {
-      if (v0 != 0) issue(v0);
+    // Fold the step at vector v0 from buffer d.
+    auto fold = [&](const Vec<S>(&d)[U], int32_t v0) {
       elem_t<S> v[K];
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int e = 0; e < KV; ++e) v[u * KV + e] = a[u].e[e];
+        for (int e = 0; e < KV; ++e) v[u * KV + e] = d[u].e[e];
       Term t[K];
       terms(v, t);
       // term (u, e) is element e of vector v0 + 64 u + lane
@@ -687,7 +691,21 @@ struct TileWave {
         else
           fd.next(off, lo, S_, lane);
       }
+    };
+    // Steps in pairs, the two buffers taking turns, so that no buffer is
+    // copied (a copy would wait for the loads in flight).
+    // Every pair the loop starts has both steps (an odd last step follows
+    // it), so the loads of each buffer are always folded before the buffer
+    // is loaded again.
+    constexpr int32_t kStep = 64 * U;
+    int32_t v0 = 0;
+    for (; v0 + kStep < nvt; v0 += 2 * kStep) {
+      issue(nx, v0 + kStep);
+      fold(a, v0);
+      if (v0 + 2 * kStep < nvt) issue(a, v0 + 2 * kStep);
+      fold(nx, v0 + kStep);
     }
+    if (v0 < nvt) fold(a, v0);
     if (last_tile && g.tail_start < g.n) scalar_step((int32_t)(g.tail_start - base), len);
 
     // The segment open at the tile's end: it ends exactly there, or runs on.
