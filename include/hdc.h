@@ -400,8 +400,17 @@ hdc_status hdc_tuning_bucket(int64_t n, int32_t* bucket);
  * "op dtype acc bucket block unroll grid_mult chunk small_seg seg_per_wave
  * [passes]" (passes may be left out: 2), '#' starts a
  * comment line.  NULL reads the path in the HDC_TUNE_CACHE environment
- * variable (which is also read once, before the first call).  A missing file
- * is not an error; a malformed line is reported and skipped. */
+ * variable (which is also read once, before the first call, unless the
+ * environment sets HDC_TUNE=0: then no cache is read at start-up and the
+ * built-in defaults apply until a caller loads or sets tuning explicitly).
+ * A missing file is not an error; a malformed line is reported and skipped.
+ *
+ * Environment: HDC_LOG set to anything but "0" prints one line per call on
+ * stderr with the dispatch decision: operation, storage and fold types, the
+ * element count and its size bucket, the tuning fields taken, the schedule
+ * they select (one or two launches; tiled or planned segmented schedule;
+ * one or three scan passes; vector or scalar map) and where the workspace
+ * came from (the caller's, the library's buffer, the static scratch array). */
 hdc_status hdc_load_tuning(const char* path);
 
 const char* hdc_status_string(hdc_status s);

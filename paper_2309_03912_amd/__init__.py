@@ -23,7 +23,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # build used by the CPU sanitizer test); there is no fallback either way.
 LIB_PATH = os.environ.get("HDC_LIBRARY") or os.path.join(HERE, "libhdc.so")
 # Tuning cache written by the autotuner for gfx950; loaded with the library
-# unless HDC_TUNE_CACHE names another one.
+# unless HDC_TUNE_CACHE names another one (which the library reads itself) or
+# HDC_TUNE=0 asks for the built-in defaults.
 TUNING_CACHE = os.path.join(HERE, "tuning_gfx950.txt")
 
 # C enums (hdc.h)
@@ -120,7 +121,8 @@ def lib() -> ctypes.CDLL:
         L.hdc_version.argtypes = []
         L.hdc_version.restype = ctypes.c_int32
         _lib = L
-        if not os.environ.get("HDC_TUNE_CACHE") and os.path.exists(TUNING_CACHE):
+        if (not os.environ.get("HDC_TUNE_CACHE") and os.environ.get("HDC_TUNE", "1") != "0"
+                and os.path.exists(TUNING_CACHE)):
             _check(L.hdc_load_tuning(TUNING_CACHE.encode()))
     return _lib
 

@@ -126,6 +126,66 @@ hdc_status load_tuning_file(const char* path) {
   return st;
 }
 
+// HDC_LOG set to anything but "0": one line per dispatch decision on stderr.
+bool log_on() {
+  static const bool on = [] {
+    const char* p = getenv("HDC_LOG");
+    return p && *p && strcmp(p, "0") != 0;
+  }();
+  return on;
+}
+
+void log_line(const char* fmt, ...) {
+  if (!log_on()) return;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> g(mu);
+  va_list ap;
+  va_start(ap, fmt);
+  fputs("hdc: ", stderr);
+  vfprintf(stderr, fmt, ap);
+  fputc('\n', stderr);
+  va_end(ap);
+}
+
+const char* dtype_name(hdc_dtype dt) {
+  switch (dt) {
+    case HDC_F32: return "f32";
+    case HDC_F16: return "f16";
+    case HDC_BF16: return "bf16";
+    case HDC_I32: return "i32";
+    default: return "?";
+  }
+}
+
+const char* acc_name(hdc_accum acc) {
+  switch (acc) {
+    case HDC_ACC_PLAIN: return "plain";
+    case HDC_ACC_COMPENSATED: return "compensated";
+    case HDC_ACC_EXACT_INT: return "exact_int";
+    case HDC_ACC_EXACT: return "exact";
+    default: return "?";
+  }
+}
+
+// The decision of one call: operation, types, size and its bucket, the
+// tuning taken, the schedule it selects and where the workspace came from.
+void log_dispatch(const char* op, hdc_dtype dt, hdc_accum acc, int64_t n, const Tuning& t, const char* schedule,
+                  const char* ws_from) {
+  if (!log_on()) return;
+  log_line("%s dtype=%s acc=%s n=%lld bucket=%d block=%d unroll=%d grid_mult=%d chunk=%d small_seg=%d "
+           "seg_per_wave=%d passes=%d schedule=%s workspace=%s",
+           op, dtype_name(dt), acc_name(acc), (long long)n, bucket_of(n), t.block, t.unroll, t.grid_mult, t.chunk,
+           t.small_seg, t.seg_per_wave, t.passes, schedule, ws_from);
+}
+
+// HDC_TUNE=0: no tuning cache is read at start-up (HDC_TUNE_CACHE is
+// ignored); the built-in defaults apply until a caller loads or sets tuning
+// explicitly.
+bool tune_cache_on() {
+  const char* p = getenv("HDC_TUNE");
+  return !(p && strcmp(p, "0") == 0);
+}
+
 // Defaults are set, and the cache named by HDC_TUNE_CACHE read, once: before
 // the first lookup and before any explicit load or set, so neither can be
 // overwritten by the defaults afterwards.
@@ -141,7 +201,14 @@ void ensure_tuning_loaded() {
       for (auto& per_acc : per_dt)
         for (Tuning& t : per_acc) t.chunk = 32768;
     const char* p = getenv("HDC_TUNE_CACHE");
-    if (p && *p) load_tuning_file(p);
+    if (p && *p) {
+      if (!tune_cache_on()) {
+        log_line("HDC_TUNE=0: tuning cache %s not read, built-in defaults", p);
+      } else {
+        const hdc_status r = load_tuning_file(p);
+        log_line("tuning cache %s read at start-up: %s", p, hdc_status_string(r));
+      }
+    }
   });
 }
 
@@ -357,6 +424,8 @@ hdc_status hdc_map(const hdc_functor* f, hdc_dtype dt, const void* x, void* y, i
   if (xb != yb && xb < yb + len && yb < xb + len)
     return fail(HDC_ERR_INVALID_ARGUMENT, "x and y overlap partially");
   const Tuning t = tuning_for(HDC_OP_MAP, dt, HDC_ACC_PLAIN, n);
+  log_dispatch("map", dt, HDC_ACC_PLAIN, n, t,
+               ((uintptr_t)x % 16) == ((uintptr_t)y % 16) ? "16-byte vectors" : "scalar (x, y misaligned)", "none");
   hipStream_t st = (hipStream_t)stream;
   return run_map(*f, dt, x, y, n, t, st);
 }
@@ -404,6 +473,13 @@ static hdc_status reduce_common(const hdc_functor* f, const hdc_functor* fm, hdc
   const Tuning t = tuning_for(op, dt, acc, n);
   uint64_t* ticket = nullptr;
   if (t.passes == 1) HDC_TRY(ticket_for(ws, &ticket));
+  if (log_on()) {
+    const bool own = acc == HDC_ACC_EXACT && !fused && (f->id == HDC_FN_PRODUCT || dt == HDC_BF16);
+    log_dispatch(fused ? "map_reduce" : f->id == HDC_FN_PRODUCT ? "dot" : "transform_reduce", dt, acc, n, t,
+                 own ? "exact kernel and its final fold (two launches)"
+                     : t.passes == 1 ? "one launch (the last block folds the partials)" : "two launches",
+                 noalloc ? "static scratch" : workspace ? "caller" : "library");
+  }
 
   if (!fused) return run_reduce(*f, dt, x, z, n, acc, out, ws, ticket, t, st);
   switch (dt) {
@@ -476,6 +552,8 @@ hdc_status hdc_segmented_reduce(const hdc_functor* f, hdc_dtype dt, const void* 
     total_bound = total;
   }
   const Tuning t = tuning_for(HDC_OP_SEGMENTED_REDUCE, dt, acc, total_bound);
+  log_dispatch("segmented_reduce", dt, acc, total_bound, t, t.passes == 1 ? "tiled" : "planned",
+               workspace ? "caller" : "library");
   return run_segmented(*f, dt, x, offsets, num_segments, acc, out, ws, cap_bytes, t, st);
 }
 
@@ -511,6 +589,8 @@ hdc_status hdc_batch_map_reduce(const hdc_functor* f, const hdc_functor* g, hdc_
   if (need < reduce_workspace_bytes()) need = reduce_workspace_bytes();  // calls run one by one reuse it
   HDC_TRY(resolve_workspace(workspace, ws_bytes, need, st, &ws));
   const size_t cap = workspace ? ws_bytes : need;  // the library's buffer holds at least `need`
+  log_dispatch("batch_map_reduce", dt, acc, total / count, t, f ? "grouped map + reduce" : "grouped reduce",
+               workspace ? "caller" : "library");
 
   // Calls whose x and y disagree in 16-byte alignment run one by one; the
   // rest go in groups of up to kBatchMax calls.
@@ -548,6 +628,7 @@ hdc_status hdc_host_map(const hdc_functor* f, hdc_dtype dt, const void* x, void*
   const uintptr_t xb = (uintptr_t)x, yb = (uintptr_t)y, len = (uintptr_t)n * elem_size(dt);
   if (xb != yb && xb < yb + len && yb < xb + len)
     return fail(HDC_ERR_INVALID_ARGUMENT, "x and y overlap partially");
+  log_line("host_map dtype=%s n=%lld threads=%d (0: every core)", dtype_name(dt), (long long)n, (int)nthreads);
   return run_host_map(*f, dt, x, y, n, nthreads);
 }
 
@@ -564,6 +645,8 @@ hdc_status hdc_host_transform_reduce(const hdc_functor* f, hdc_dtype dt, const v
     HDC_TRY(check_ptr(z, dt, n, "z"));
   }
   if (!out) return fail(HDC_ERR_INVALID_ARGUMENT, "out is NULL");
+  log_line("host_transform_reduce dtype=%s acc=%s n=%lld threads=%d (0: every core)", dtype_name(dt), acc_name(acc),
+           (long long)n, (int)nthreads);
   return run_host_reduce(*f, dt, x, z, n, acc, out, nthreads);
 }
 
@@ -587,6 +670,8 @@ hdc_status hdc_scan(const hdc_functor* f, hdc_dtype dt, const void* x, void* y, 
   const Tuning t = tuning_for(HDC_OP_SCAN, dt, acc, n);
   void* ws = nullptr;
   HDC_TRY(resolve_workspace(workspace, ws_bytes, scan_workspace_bytes(n), st, &ws));
+  log_dispatch(exclusive ? "scan (exclusive)" : "scan (inclusive)", dt, acc, n, t,
+               t.unroll == 1 ? "three passes" : "one pass (tree carry)", workspace ? "caller" : "library");
   return run_scan(*f, dt, x, y, n, acc, exclusive, ws, t, st);
 }
 
@@ -613,6 +698,8 @@ hdc_status hdc_segmented_scan(const hdc_functor* f, hdc_dtype dt, const void* x,
   const Tuning t = tuning_for(HDC_OP_SCAN, dt, acc, total);
   void* ws = nullptr;
   HDC_TRY(resolve_workspace(workspace, ws_bytes, scan_workspace_bytes(total), st, &ws));
+  log_dispatch(exclusive ? "segmented_scan (exclusive)" : "segmented_scan (inclusive)", dt, acc, total, t,
+               t.unroll == 1 ? "three passes" : "one pass (tree carry)", workspace ? "caller" : "library");
   return run_segmented_scan(*f, dt, x, offsets, num_segments, y, total, acc, exclusive, ws, t, st);
 }
 
