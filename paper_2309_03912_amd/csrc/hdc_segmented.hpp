@@ -479,6 +479,35 @@ __host__ __device__ __forceinline__ int64_t tile_of(const TileGeom& g, int64_t t
 // evenly spaced offsets and narrows the range to one gap between probes;
 // the final round loads the (at most) 64 offsets of the range, which become
 // the boundary batch.  For 100,000 segments: three rounds.
+// The terms of one step of the tiled pass.  A Horner polynomial runs its
+// degree as a loop bound: each round reads its coefficient from the callable
+// by index (one scalar load), so no coefficient occupies a scalar register
+// across the kernel and a step costs d rounds of K fmas.  A switch into a
+// straight chain at the degree (the small-batch form of eval_batch) was
+// compiled into predicated stages that each re-set the K accumulators, ~64
+// extra moves per step at degree 8.  The fma sequence is eval_batch's: the
+// same bits.
+template <class F, int K>
+__device__ __forceinline__ void step_terms(const F& f, float (&t)[K]) {
+  if constexpr (std::is_same_v<F, Horner>) {
+    const int d = f.degree;
+    const float top = f.c[d];
+    float acc[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) acc[i] = top;
+#pragma unroll 1
+    for (int k = d - 1; k >= 0; --k) {
+      const float ck = f.c[k];
+#pragma unroll
+      for (int i = 0; i < K; ++i) acc[i] = __builtin_fmaf(acc[i], t[i], ck);
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i) t[i] = acc[i];
+  } else {
+    eval_batch<F, K, true>(f, t);
+  }
+}
+
 struct SegFinder {
   int64_t p;
   int32_t a, n;     // off[a] - off[0] <= p; the answer is in [a, a + n)
@@ -609,7 +638,7 @@ struct TileWave {
       float w[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) w[k] = S::widen(v[k]);
-      eval_batch<F, K, true>(f, w);
+      step_terms<F, K>(f, w);
 #pragma unroll
       for (int k = 0; k < K; ++k) t[k] = w[k];
     }
