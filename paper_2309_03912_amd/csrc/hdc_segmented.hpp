@@ -568,11 +568,21 @@ struct TileWave {
     const int64_t i = (int64_t)b + lane;
     bnd = i <= S_ ? off[i] - lo : INT64_MAX;
   }
-  // off[i] - off[0] - base, clamped to len + 1, from the batch (reloaded when passed)
+  // off[i] - off[0] - base, clamped to len + 1: from the batch when it
+  // holds offset i, else read on its own (a uniform load)
   __device__ int32_t bound(int32_t i) {
-    if (i - bbase >= 64) load_batch(i);
-    const int64_t v = read_lane(bnd, i - bbase) - base;
+    int64_t v;
+    if (i - bbase < 64)
+      v = read_lane(bnd, i - bbase);
+    else
+      v = i <= S_ ? off[i] - lo : INT64_MAX;
+    v -= base;
     return v <= len ? (int32_t)v : len + 1;
+  }
+  // Before a step: a batch more than half used is reloaded from the next
+  // segment end on, so the boundaries of a step read their offsets from it.
+  __device__ void refill() {
+    if (j + 1 - bbase >= 32) load_batch(j + 1);
   }
 
   // The segment holding tile position 0 (the last j with off[j] - off[0] <=
@@ -606,10 +616,13 @@ struct TileWave {
     started = true;
   }
 
-  // Add a step's terms.  Term k sits at tile position ps + rel(k) and exists
-  // iff kFull or ok(k); every position of the step lies in [ps, pe).
-  template <bool kFull, class Rel, class Ok>
-  __device__ void step(const Term (&t)[K], Rel rel, Ok ok, int32_t ps, int32_t pe) {
+  // Add a step's terms.  Term k sits at tile position ps + lp + dk(k), with
+  // lp this lane's offset and dk(k) a constant, and exists iff kFull or
+  // ok(k); every position of the step lies in [ps, pe).  A bound on the
+  // position is a uniform bound on lp, so the step keeps one per-lane value
+  // instead of K.
+  template <bool kFull, class Dk, class Ok>
+  __device__ void step(const Term (&t)[K], int32_t lp, Dk dk, Ok ok, int32_t ps, int32_t pe) {
     if (nb >= pe) {  // no boundary inside the step (uniform)
 #pragma unroll
       for (int k = 0; k < K; ++k)
@@ -620,14 +633,15 @@ struct TileWave {
     while (nb < pe) {
       const int32_t end = nb - ps;
 #pragma unroll
-      for (int k = 0; k < K; ++k) acc.add((kFull || ok(k)) && rel(k) >= prev && rel(k) < end ? t[k] : Term{});
+      for (int k = 0; k < K; ++k)
+        acc.add((kFull || ok(k)) && lp >= prev - dk(k) && lp < end - dk(k) ? t[k] : Term{});
       finish(wave_reduce(acc, MergeOp<Acc>{}));
       acc = Acc::zero();
       prev = end;
       advance();
     }
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc.add((kFull || ok(k)) && rel(k) >= prev ? t[k] : Term{});
+    for (int k = 0; k < K; ++k) acc.add((kFull || ok(k)) && lp >= prev - dk(k) ? t[k] : Term{});
   }
 
   __device__ void terms(const elem_t<S> (&v)[K], Term (&t)[K]) {
@@ -652,7 +666,7 @@ struct TileWave {
     for (int k = 0; k < K; ++k) v[k] = k == 0 && mine ? x[base + p0 + lane] : elem_t<S>{};
     Term t[K];
     terms(v, t);
-    step<false>(t, [&](int) { return lane; }, [&](int k) { return k == 0 && mine; }, p0, p1);
+    step<false>(t, lane, [](int) { return 0; }, [&](int k) { return k == 0 && mine; }, p0, p1);
   }
 
   // Tile position 0 of tile t, relative to off[0].
@@ -698,6 +712,7 @@ struct TileWave {
     if (first_tile && g.head > 0) scalar_step(0, (int32_t)g.head);
     // Fold the step at vector v0 from buffer d.
     auto fold = [&](const Vec<S>(&d)[U], int32_t v0) {
+      refill();
       elem_t<S> v[K];
 #pragma unroll
       for (int u = 0; u < U; ++u)
@@ -705,14 +720,15 @@ struct TileWave {
         for (int e = 0; e < KV; ++e) v[u * KV + e] = d[u].e[e];
       Term t[K];
       terms(v, t);
-      // term (u, e) is element e of vector v0 + 64 u + lane
-      auto rel = [&](int k) { return ((k / KV) * 64 + lane) * KV + k % KV; };
+      // term (u, e) is element e of vector v0 + 64 u + lane: step position
+      // lane * KV + (64 u KV + e)
+      auto dk = [](int k) { return (k / KV) * 64 * KV + k % KV; };
       const int32_t ps = vpos + v0 * KV;
       if (v0 + 64 * U <= nvt) {
-        step<true>(t, rel, [](int) { return true; }, ps, ps + 64 * U * KV);
+        step<true>(t, lane * KV, dk, [](int) { return true; }, ps, ps + 64 * U * KV);
       } else {
         const int32_t nv = nvt - v0;
-        step<false>(t, rel, [&](int k) { return (k / KV) * 64 + lane < nv; }, ps, ps + nv * KV);
+        step<false>(t, lane * KV, dk, [&](int k) { return lane < nv - (k / KV) * 64; }, ps, ps + nv * KV);
       }
       if (searching) {  // one round of the next tile's search per step
         if (fd.final_round())
