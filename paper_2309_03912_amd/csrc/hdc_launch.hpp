@@ -88,13 +88,16 @@ hdc_status launch_reduce(const F& f, const void* x, const void* z, int64_t n, vo
 }
 
 
-// Exact bf16 sum: pass 1 over t.block threads x t.unroll vectors per step
-// (1, 2 or 4), at most 4096 blocks (their 88-byte partials fit the reduce
-// workspace), then the one-block final combine and rounding.
-inline hdc_status launch_exact_bf16(const void* x, int64_t n, void* out, void* ws, const Tuning& t,
+// Exact bf16 sum: pass 1 over t.block threads (at most kExactMaxBlock: the
+// digit accumulators take 64 bytes of LDS per thread) x t.unroll vectors per
+// step (1, 2 or 4), at most 4096 blocks (their 88-byte partials fit the
+// reduce workspace), then the one-block final combine and rounding.
+inline hdc_status launch_exact_bf16(const void* x, int64_t n, void* out, void* ws, const Tuning& tuned,
                                     hipStream_t st) {
   int cus = 0;
   HDC_TRY(compute_units(&cus));
+  Tuning t = tuned;
+  if (t.block > kExactMaxBlock) t.block = kExactMaxBlock;
   const Range r = make_range<BF16>(x, n, true);
   const int u = t.unroll >= 4 ? 4 : t.unroll;
   int64_t g = grid_for(r.nvec, (int64_t)t.block * u, cus, t);
@@ -110,12 +113,13 @@ inline hdc_status launch_exact_bf16(const void* x, int64_t n, void* out, void* w
   Bf16Exact* partials = static_cast<Bf16Exact*>(ws);
   const uint16_t* xp = static_cast<const uint16_t*>(x);
   const dim3 grid((unsigned)g), block(t.block);
+  const size_t lds = sizeof(double) * kExactFoldDigits * (size_t)t.block;
   if (u == 1)
-    exact_bf16_kernel<1><<<grid, block, 0, st>>>(xp, r, partials);
+    exact_bf16_kernel<1><<<grid, block, lds, st>>>(xp, r, partials);
   else if (u == 2)
-    exact_bf16_kernel<2><<<grid, block, 0, st>>>(xp, r, partials);
+    exact_bf16_kernel<2><<<grid, block, lds, st>>>(xp, r, partials);
   else
-    exact_bf16_kernel<4><<<grid, block, 0, st>>>(xp, r, partials);
+    exact_bf16_kernel<4><<<grid, block, lds, st>>>(xp, r, partials);
   HDC_TRY(check_launch("exact bf16 launch"));
   exact_bf16_final_kernel<<<dim3(1), dim3(256), 0, st>>>(partials, (int)g, static_cast<double*>(out));
   return check_launch("exact bf16 final launch");
