@@ -268,6 +268,46 @@ struct ScanWave {
     }
   }
 
+  // The lane state that emit needs, as 32-bit words: the terms (float
+  // storage) or the elements (int32), the chunk prefixes and the heads.
+  static constexpr int kStashWords =
+      kScanE + Q * (int)(sizeof(Acc) / 4) + (kSeg ? 1 : 0);
+  // Park that state in LDS (word c of lane l at s[c * 64 + l]) and take it
+  // back: a wavefront that runs the carry's polls between the two holds none
+  // of it in registers meanwhile.
+  __device__ void stash(uint32_t* s) const {
+    int c = 0;
+    auto put = [&](const auto& v) {
+      uint32_t w[sizeof(v) / 4];
+      __builtin_memcpy(w, &v, sizeof(v));
+#pragma unroll
+      for (int i = 0; i < (int)(sizeof(v) / 4); ++i) s[(c + i) * 64 + lane] = w[i];
+      c += (int)(sizeof(v) / 4);
+    };
+    if constexpr (std::is_same_v<S, I32>)
+      put(v);
+    else
+      put(t);
+    put(ex);
+    if constexpr (kSeg) put(hmask);
+  }
+  __device__ void unstash(const uint32_t* s) {
+    int c = 0;
+    auto get = [&](auto& v) {
+      uint32_t w[sizeof(v) / 4];
+#pragma unroll
+      for (int i = 0; i < (int)(sizeof(v) / 4); ++i) w[i] = s[(c + i) * 64 + lane];
+      __builtin_memcpy(&v, w, sizeof(v));
+      c += (int)(sizeof(v) / 4);
+    };
+    if constexpr (std::is_same_v<S, I32>)
+      get(v);
+    else
+      get(t);
+    get(ex);
+    if constexpr (kSeg) get(hmask);
+  }
+
   __device__ bool is_head(int q, int e) const {
     if constexpr (kSeg)
       return (hmask >> (q * V + e)) & 1u;
@@ -810,6 +850,7 @@ scan_onepass_kernel(F f, const elem_t<S>* x, int64_t n, SegSpec seg,
   __shared__ uint32_t heads_sh[IsSeg<Acc>::value ? kTileWords : 1];
   __shared__ int64_t first_sh;
   __shared__ u32x4 stage_sh[kStageVecs<S, Acc>];
+  __shared__ uint32_t park_sh[IsSeg<Acc>::value ? ScanWave<F, S, Acc>::kStashWords * 64 : 1];
   if (threadIdx.x == 0) tile_sh = (int64_t)atomicAdd(lb.ticket, 1u);
   __syncthreads();
   const int64_t tile = tile_sh;
@@ -821,8 +862,13 @@ scan_onepass_kernel(F f, const elem_t<S>* x, int64_t n, SegSpec seg,
   Acc total;
   const Acc before = block_wave_prefix(w.wave_total, lds, &total);
   if (threadIdx.x < 64) {
+    // Segmented scans park wavefront 0's lane state in LDS while it polls:
+    // the polls and the lane state together needed ~70 VGPRs, over the 64
+    // that two 1024-thread blocks per CU allow.
+    if constexpr (IsSeg<Acc>::value) w.stash(park_sh);
     const typename C::T carry = scan_tree_carry<C>(lb, tile, (int64_t)gridDim.x, C::of(total), slots);
     if (threadIdx.x == 0) carry_sh = carry;
+    if constexpr (IsSeg<Acc>::value) w.unstash(park_sh);
   }
   __syncthreads();
   w.template emit<kOutAligned>(f, Acc::merge(C::to(carry_sh), before), exclusive, y,
