@@ -5,11 +5,11 @@
 // position q in [0, 253] (q = E - 1 for a biased exponent E >= 1, q = 0 for
 // subnormals).  Writing q = 32 d + r, the value is (m << r) * 2^(32 d - 133):
 // an integer below 2^39 added to digit d (d in [0, 7]) of a fixed-point
-// number whose digit j has the unit 2^(32 j - 133).  Each lane keeps its
-// digits in int64 registers (carry-save: no carries while folding); a
-// wavefront learns which digits its current batch touches from eight ballots
-// and updates only those.  Lanes, wavefronts and blocks add digit by digit
-// (integer additions: exact and order-free), and the final combine
+// number whose digit j has the unit 2^(32 j - 133).  Each thread keeps its
+// eight digits as fp64 accumulators in LDS (integers below 2^53, so every
+// add is exact; no carries while folding) and adds each term to its digit
+// by address.  Lanes, wavefronts and blocks then add digit by digit as
+// int64 (integer additions: exact and order-free), and the final combine
 // propagates the carries into 32-bit digits and rounds the whole number to
 // nearest-even fp64 once.  Infinities and NaNs are tracked as flags with the
 // IEEE outcome of their sum (NaN if a NaN or both infinities appear).

@@ -474,11 +474,6 @@ __host__ __device__ __forceinline__ int64_t tile_of(const TileGeom& g, int64_t t
   return t < g.ntiles - 1 ? t : g.ntiles - 1;
 }
 
-// Search for the segment holding position p (relative to off[0]), one round
-// at a time so that the rounds can overlap other work: a round probes 64
-// evenly spaced offsets and narrows the range to one gap between probes;
-// the final round loads the (at most) 64 offsets of the range, which become
-// the boundary batch.  For 100,000 segments: three rounds.
 // The terms of one step of the tiled pass.  A Horner polynomial runs its
 // degree as a loop bound: each round reads its coefficient from the callable
 // by index (one scalar load), so no coefficient occupies a scalar register
@@ -508,6 +503,11 @@ __device__ __forceinline__ void step_terms(const F& f, float (&t)[K]) {
   }
 }
 
+// Search for the segment holding position p (relative to off[0]), one round
+// at a time so that the rounds can overlap other work: a round probes 64
+// evenly spaced offsets and narrows the range to one gap between probes;
+// the final round loads the (at most) 64 offsets of the range, which become
+// the boundary batch.  For 100,000 segments: three rounds.
 struct SegFinder {
   int64_t p;
   int32_t a, n;     // off[a] - off[0] <= p; the answer is in [a, a + n)
