@@ -503,37 +503,43 @@ __device__ __forceinline__ void step_terms(const F& f, float (&t)[K]) {
   }
 }
 
-// Search for the segment holding position p (relative to off[0]), one round
-// at a time so that the rounds can overlap other work: a round probes 64
-// evenly spaced offsets and narrows the range to one gap between probes;
-// the final round loads the (at most) 64 offsets of the range, which become
-// the boundary batch.  For 100,000 segments: three rounds.
+// Search for the segment holding absolute position p (the last j with
+// off[j] <= p), one round at a time so that the rounds can overlap other
+// work: a round probes 64 evenly spaced offsets and narrows the range to one
+// gap between probes; the final round loads the (at most) 64 offsets of the
+// range, which become the boundary batch.  For 100,000 segments: three
+// rounds.  The probes are absolute offsets, so the first round needs no
+// target yet (begin, then aim) and can go out before off[0] is known.
 struct SegFinder {
   int64_t p;
-  int32_t a, n;     // off[a] - off[0] <= p; the answer is in [a, a + n)
+  int32_t a, n;     // off[a] <= p; the answer is in [a, a + n)
   int32_t step;     // spacing of the round in flight (1: the final round)
-  int64_t probe;    // this lane's probe of the round in flight, minus off[0]; INT64_MAX if none
+  int64_t probe;    // this lane's probe of the round in flight; INT64_MAX if none
 
-  __device__ void issue(const int64_t* off, int64_t lo, int32_t S, int lane) {
+  __device__ void issue(const int64_t* off, int32_t S, int lane) {
     step = n > 64 ? (n + 63) / 64 : 1;
     const int64_t idx = (int64_t)a + (int64_t)lane * step;
     const bool ok = step == 1 ? idx <= S : idx < (int64_t)a + n;
-    probe = ok ? off[idx] - lo : INT64_MAX;
+    probe = ok ? off[idx] : INT64_MAX;
   }
-  __device__ void start(const int64_t* off, int64_t lo, int32_t S, int64_t p_, int lane) {
-    p = p_;
+  __device__ void begin(const int64_t* off, int32_t S, int lane) {
     a = 0;
     n = S + 1;
-    issue(off, lo, S, lane);
+    issue(off, S, lane);
+  }
+  __device__ void aim(int64_t p_) { p = p_; }
+  __device__ void start(const int64_t* off, int32_t S, int64_t p_, int lane) {
+    aim(p_);
+    begin(off, S, lane);
   }
   __device__ bool final_round() const { return step == 1; }
   // Consume a non-final round and issue the next one.
-  __device__ void next(const int64_t* off, int64_t lo, int32_t S, int lane) {
+  __device__ void next(const int64_t* off, int32_t S, int lane) {
     const int cnt = __builtin_popcountll(__builtin_amdgcn_ballot_w64(probe <= p));  // a prefix of the lanes
     const int32_t na = a + (cnt - 1) * step;
     n = a + n - na < step ? a + n - na : step;
     a = na;
-    issue(off, lo, S, lane);
+    issue(off, S, lane);
   }
 };
 
@@ -588,9 +594,9 @@ struct TileWave {
   // The segment holding tile position 0 (the last j with off[j] - off[0] <=
   // base), from a finder started for `base`: its remaining rounds run here.
   __device__ void locate(SegFinder& fd) {
-    while (!fd.final_round()) fd.next(off, lo, S_, lane);
+    while (!fd.final_round()) fd.next(off, S_, lane);
     bbase = fd.a;
-    bnd = fd.probe;
+    bnd = fd.probe == INT64_MAX ? INT64_MAX : fd.probe - lo;
     const int cnt = __builtin_popcountll(__builtin_amdgcn_ballot_w64(lane < fd.n && bnd <= base));
     j = fd.a + cnt - 1;
     started = read_lane(bnd, j - bbase) >= base;
@@ -703,9 +709,10 @@ struct TileWave {
     // holding the tile's first element finishes (three dependent rounds of
     // offsets, most of them already run during the previous tile).
     if (nvt > 0) issue(a, 0);
-    if (!have) fd.start(off, lo, S_, base, lane);
+    if (!have) fd.begin(off, S_, lane);
+    fd.aim(lo + base);
     locate(fd);
-    if (next >= 0) fd.start(off, lo, S_, tile_base(g, st.tile_vecs, next), lane);
+    if (next >= 0) fd.start(off, S_, lo + tile_base(g, st.tile_vecs, next), lane);
     bool searching = next >= 0;
     acc = Acc::zero();
 
@@ -734,7 +741,7 @@ struct TileWave {
         if (fd.final_round())
           searching = false;
         else
-          fd.next(off, lo, S_, lane);
+          fd.next(off, S_, lane);
       }
     };
     // Steps in pairs, the two buffers taking turns, so that no buffer is
@@ -775,6 +782,10 @@ __global__ __launch_bounds__(1024) void seg_tiles_kernel(F f, const elem_t<S>* _
   const int64_t wpb = blockDim.x >> 6;
   const int64_t w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * wpb + (threadIdx.x >> 6)));
   const int64_t W = (int64_t)gridDim.x * wpb;
+  // The first round of the first tile's search goes out with the loads of
+  // the tile geometry (it needs no position yet).
+  SegFinder fd{};
+  fd.begin(off, (int32_t)S_, lane);
   const TileGeom g = tile_geom<S>(x, off, S_, st.tile_vecs);
   if (g.ntiles > st.cap) {
     // More tiles than the workspace holds: every segment is folded whole by one wavefront.
@@ -784,8 +795,7 @@ __global__ __launch_bounds__(1024) void seg_tiles_kernel(F f, const elem_t<S>* _
     }
     return;
   }
-  SegFinder fd{};
-  bool have = false;
+  bool have = true;
   for (int64_t t = w; t < g.ntiles; t += W) {
     TileWave<F, S, Acc, U> tw{f, x + g.lo, off, g.lo, (int32_t)S_, st, out, lane, (int32_t)t};
     const int64_t next = t + W < g.ntiles ? t + W : -1;
