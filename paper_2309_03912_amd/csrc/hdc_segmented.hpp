@@ -748,13 +748,17 @@ struct TileWave {
     // copied (a copy would wait for the loads in flight).
     // Every pair the loop starts has both steps (an odd last step follows
     // it), so the loads of each buffer are always folded before the buffer
-    // is loaded again.
+    // is loaded again.  The loads for the step after the pair go out
+    // unconditionally (past the tile's end they read its last vector again
+    // and are never folded): a load issued on one path only makes the
+    // compiler's wait for the other buffer count it as absent, so the next
+    // fold would wait for every load in flight.
     constexpr int32_t kStep = 64 * U;
     int32_t v0 = 0;
     for (; v0 + kStep < nvt; v0 += 2 * kStep) {
       issue(nx, v0 + kStep);
       fold(a, v0);
-      if (v0 + 2 * kStep < nvt) issue(a, v0 + 2 * kStep);
+      issue(a, v0 + 2 * kStep);
       fold(nx, v0 + kStep);
     }
     if (v0 < nvt) fold(a, v0);
