@@ -174,20 +174,25 @@ __device__ __forceinline__ void store_result(void* out, int64_t j, const Acc& a)
 }
 
 // Fold items get(0), ..., get(m - 1) with one wavefront: lane l folds items
-// l, l + 64, ... in order, eight loads in flight, then the lanes meet in
-// wave_reduce.  Every lane must be active; every lane returns the total.
+// l, l + 64, ... in order, then the lanes meet in wave_reduce.  Every lane
+// must be active; every lane returns the total.  A round has 16 loads per
+// lane in flight, all issued unconditionally (past m a lane reads item m - 1
+// again and does not fold it): loads on a lane-dependent condition made each
+// round wait for its loads one at a time, and a segment spanning 16,000
+// tiles took ~60 us to combine.
 template <class V, class Op, class Get>
 __device__ __forceinline__ V wave_fold_items(Get get, int64_t m, int lane, Op op, V zero) {
+  constexpr int kRound = 16;
   V acc = zero;
-  for (int64_t base = 0; base < m; base += 8 * 64) {
-    V v[8];
+  for (int64_t base = 0; base < m; base += kRound * 64) {
+    V v[kRound];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < kRound; ++u) {
       const int64_t k = base + u * 64 + lane;
-      v[u] = k < m ? get(k) : zero;
+      v[u] = get(k < m ? k : m - 1);
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < kRound; ++u)
       if (base + u * 64 + lane < m) acc = op(acc, v[u]);
   }
   return wave_reduce(acc, op);
