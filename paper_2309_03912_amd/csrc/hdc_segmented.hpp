@@ -701,13 +701,23 @@ struct TileWave {
     // Two steps of loads in flight: step s + 1's loads go out before step s
     // is folded.
     Vec<S> a[U], nx[U];
-    // Lanes past the tile's last vector load that vector again (the partial
-    // step masks their terms out), so no register is written before its load.
+    // The loads of a step go through a raw buffer resource (stride 0, word 3
+    // 0x00020000: 32-bit data format, no swizzle) based at the step's first
+    // vector and ending at the tile's last one.  The hardware checks each
+    // lane's byte offset against that range and returns zeros past it, with
+    // no memory access (the partial step masks those terms out).  The lane
+    // offsets stay fixed; only the base, in scalar registers, moves from step
+    // to step, so no vector register is written before a load but the
+    // load's own.  Cache policy 2: non-temporal.
+    const int32_t lane_off = lane * 16;
     auto issue = [&](Vec<S>(&d)[U], int32_t v0) {
+      const int32_t left = v0 < nvt ? (nvt - v0) * 16 : 0;
+      const __amdgpu_buffer_rsrc_t rs =
+          __builtin_amdgcn_make_buffer_rsrc((void*)(xv + (int64_t)v0 * KV), (short)0, left, 0x00020000);
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int32_t vi = v0 + u * 64 + lane;
-        d[u] = load16<S>(xv + (int64_t)(vi < nvt ? vi : nvt - 1) * KV);
+        const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(rs, lane_off + u * 1024, 0, 2);
+        __builtin_memcpy(&d[u], &w, 16);
       }
     };
     // The first step's loads go out before the search for the segment
@@ -754,10 +764,10 @@ struct TileWave {
     // Every pair the loop starts has both steps (an odd last step follows
     // it), so the loads of each buffer are always folded before the buffer
     // is loaded again.  The loads for the step after the pair go out
-    // unconditionally (past the tile's end they read its last vector again
-    // and are never folded): a load issued on one path only makes the
-    // compiler's wait for the other buffer count it as absent, so the next
-    // fold would wait for every load in flight.
+    // unconditionally (past the tile's end they return zeros and are never
+    // folded): a load issued on one path only makes the compiler's wait for
+    // the other buffer count it as absent, so the next fold would wait for
+    // every load in flight.
     constexpr int32_t kStep = 64 * U;
     int32_t v0 = 0;
     for (; v0 + kStep < nvt; v0 += 2 * kStep) {
