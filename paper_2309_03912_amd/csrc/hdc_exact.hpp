@@ -111,22 +111,31 @@ struct Bf16Exact {
 // vectors per lane, kExactVecsPerLane).  The accumulators live in LDS, digit
 // j of thread i at dig[j * blockDim + i], so a term goes to its own digit by
 // address with one fp64 LDS add (no per-digit select over the batch); only
-// the thread that owns a slot touches it.  Infinities and NaNs contribute no
-// term; their flags are taken on a separate, rare path.  (Building the fp64
-// term from the bf16 bits with integer operations instead of the widening
-// and ldexp measured 20% slower.)
+// the thread that owns a slot touches it.  Infinities and NaNs are added to
+// a ninth slot that is never read (a select of the address, not of the
+// fp64 term); their flags are taken on a separate, rare path.  A term costs
+// ten vector instructions and the LDS add; the slot address is one 24-bit
+// multiply-add (with a select of the term and a 64-bit address, thirteen:
+// 9% slower at 2^28).  (Building the fp64 term from the bf16 bits with
+// integer operations instead of the widening and ldexp measured 20% slower.)
 constexpr int64_t kExactVecsPerLane = 1024;  // 8192 terms (+2 head/tail) < 2^14
-constexpr int kExactMaxBlock = 512;          // 8 digits x 8 bytes x 512 threads = 32 KiB of LDS
+constexpr int kExactMaxBlock = 512;          // 9 slots x 8 bytes x 512 threads = 36 KiB of LDS
 
 template <int U>
 __global__ __launch_bounds__(kExactMaxBlock) void exact_bf16_kernel(const uint16_t* __restrict__ x, Range r,
                                                                     Bf16Exact* partials) {
   __shared__ Bf16Exact lds[kMaxWaves];
-  extern __shared__ double dig[];  // kExactFoldDigits * blockDim
+  extern __shared__ double dig[];  // (kExactFoldDigits + 1) * blockDim
   constexpr int V = 8;
   const int64_t B = blockDim.x, tid = threadIdx.x;
 #pragma unroll
-  for (int j = 0; j < kExactFoldDigits; ++j) dig[j * B + tid] = 0.0;
+  for (int j = 0; j <= kExactFoldDigits; ++j) dig[j * B + tid] = 0.0;
+  // LDS byte address of this thread's slot of digit d: own + 8 B d = own +
+  // (32 d) (B / 4), one 24-bit multiply-add from q & 0xE0 = 32 d.  Slot
+  // kExactFoldDigits is the sink for infinities and NaNs (never read).
+  using lds_f64 = __attribute__((address_space(3))) double;
+  const uint32_t own = (uint32_t)(uintptr_t)(lds_f64*)(dig + tid), quarter = (uint32_t)B >> 2;
+  const uint32_t sink = own + 8u * (uint32_t)B * kExactFoldDigits;
   uint32_t nf = 0;
   auto fold = [&](const uint32_t (&u)[V]) {  // u: bf16 bits, 0 for no value
     bool special = false;
@@ -135,12 +144,14 @@ __global__ __launch_bounds__(kExactMaxBlock) void exact_bf16_kernel(const uint16
       const uint32_t E = (u[i] >> 7) & 0xFFu;
       special = special || E == 0xFFu;
       const uint32_t q = (E > 1u ? E : 1u) - 1u;  // E - 1, or 0 for subnormals
-      const int d = (int)(q >> 5);
+      const uint32_t d32 = q & 0xE0u;              // 32 d
       // the value itself (bf16 is the top half of binary32; subnormals are kept),
       // scaled by 2^(133 - 32 d): the signed integer m 2^(q mod 32), exact in fp64
-      const float v = __builtin_bit_cast(float, (E == 0xFFu ? 0u : u[i]) << 16);
-      const double t = __builtin_ldexp((double)v, 133 - 32 * d);
-      __hip_atomic_fetch_add(&dig[d * B + tid], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      const float v = __builtin_bit_cast(float, u[i] << 16);
+      const double t = __builtin_ldexp((double)v, 133 - (int)d32);
+      const uint32_t at = E == 0xFFu ? sink : own + d32 * quarter;
+      __hip_atomic_fetch_add((lds_f64*)(uintptr_t)at, t, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     if (__builtin_amdgcn_ballot_w64(special) != 0) {  // rare: infinities and NaNs present
 #pragma unroll

@@ -113,7 +113,7 @@ inline hdc_status launch_exact_bf16(const void* x, int64_t n, void* out, void* w
   Bf16Exact* partials = static_cast<Bf16Exact*>(ws);
   const uint16_t* xp = static_cast<const uint16_t*>(x);
   const dim3 grid((unsigned)g), block(t.block);
-  const size_t lds = sizeof(double) * kExactFoldDigits * (size_t)t.block;
+  const size_t lds = sizeof(double) * (kExactFoldDigits + 1) * (size_t)t.block;
   if (u == 1)
     exact_bf16_kernel<1><<<grid, block, lds, st>>>(xp, r, partials);
   else if (u == 2)
