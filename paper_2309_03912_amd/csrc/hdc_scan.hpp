@@ -184,28 +184,6 @@ struct SegSpec {
   int64_t m;
 };
 
-// First index i in [0, m) with off[i] >= p (m if none), by one wavefront:
-// every round probes 64 evenly spaced offsets, so 100,000 segments take three
-// rounds.  The result is wavefront-uniform.
-__device__ __forceinline__ int64_t wave_lower_bound(const int64_t* __restrict__ off, int64_t m, int64_t p,
-                                                    int lane) {
-  int64_t lo = 0, hi = m;  // the answer is in [lo, hi]; off[hi] >= p or hi == m
-  while (hi - lo > 64) {
-    const int64_t step = (hi - lo + 63) / 64;
-    int64_t idx = lo + (int64_t)(lane + 1) * step - 1;
-    if (idx > hi - 1) idx = hi - 1;
-    const uint64_t ge = __builtin_amdgcn_ballot_w64(off[idx] >= p);
-    if (ge == 0) return hi;
-    const int f = __builtin_ctzll(ge);
-    const int64_t nhi = lo + (int64_t)(f + 1) * step - 1;
-    lo = f == 0 ? lo : lo + (int64_t)f * step;
-    hi = nhi < hi - 1 ? nhi : hi - 1;
-  }
-  const bool in = lane < hi - lo;
-  const uint64_t ge = __builtin_amdgcn_ballot_w64(in && off[lo + (in ? lane : 0)] >= p);
-  return ge == 0 ? hi : lo + __builtin_ctzll(ge);
-}
-
 // One wavefront's part of a tile: loading, terms, the fold states of the
 // fixed order above, and the outputs.  For a segmented scan (Acc a SegAcc)
 // each lane takes the segment-start bits of its elements from the tile's
@@ -452,11 +430,14 @@ __device__ __forceinline__ ScanWave<F, S, Acc> scan_wave_at(int64_t tile, int64_
 }
 
 // Segment starts of the tile [t0, t0 + len) as a bitmap in LDS (len / 32
-// words; bit p: position t0 + p starts a segment), built by the whole block:
-// wavefront 0 finds the first boundary at or after t0 with a 64-way search,
-// then every thread takes one boundary per round until they pass the tile.
-// Then each wavefront takes its lanes' bits (ScanWave::take_heads).  Empty
-// segments repeat a boundary, which sets the same bit again.
+// words; bit p: position t0 + p starts a segment), built by the whole block
+// in two dependent rounds of offset reads: one probe per thread at evenly
+// spaced offsets (issued before the tile's elements are loaded, see
+// heads_probe) narrows the first boundary at or after t0 to one gap between
+// probes; then every thread takes one offset per round from the start of
+// that gap until they pass the tile.  Then each wavefront takes its lanes'
+// bits (ScanWave::take_heads).  Empty segments repeat a boundary, which sets
+// the same bit again.
 constexpr int kTileWords = 1024 * kScanE / 32;  // bitmap words of the largest tile
 
 // 16-byte vectors of output staging per block: 2 KiB per wavefront when a
@@ -465,20 +446,53 @@ template <class S, class Acc>
 constexpr int kStageVecs =
     S::kVec * sizeof(typename ScanOut<Acc>::T) == 32 ? kMaxWaves * 128 : 1;
 
+// This thread's probe for the first round: offset (tid + 1) step - 1 of the
+// m offsets (clamped to the last one), step = ceil(m / blockDim).  With m no
+// larger than the block there is no probe (step 0) and the search starts at
+// offset 0.
+struct HeadProbe {
+  int64_t step;
+  int64_t v;
+};
+
+__device__ __forceinline__ HeadProbe heads_probe(const SegSpec& seg) {
+  HeadProbe p{0, 0};
+  const int64_t nt = blockDim.x;
+  if (seg.m > nt) {
+    p.step = (seg.m + nt - 1) / nt;
+    int64_t idx = ((int64_t)threadIdx.x + 1) * p.step - 1;
+    if (idx > seg.m - 1) idx = seg.m - 1;
+    p.v = seg.off[idx];
+  }
+  return p;
+}
+
+// `wfirst` (LDS, kMaxWaves words): per wavefront, its first thread whose
+// probe is at or after t0.
 template <class W>
-__device__ void tile_heads(W& w, const SegSpec& seg, int64_t t0, int64_t len, uint32_t* bits, int64_t* first) {
-  const int tid = threadIdx.x;
-  for (int64_t i = tid; i < len / 32; i += blockDim.x) bits[i] = 0;
-  if (tid < 64) {
-    const int64_t b = wave_lower_bound(seg.off, seg.m, t0, tid);
-    if (tid == 0) *first = b;
+__device__ void tile_heads(W& w, const SegSpec& seg, const HeadProbe& pr, int64_t t0, int64_t len, uint32_t* bits,
+                           uint32_t* wfirst) {
+  const int tid = threadIdx.x, nt = blockDim.x, nw = nt >> 6;
+  for (int64_t i = tid; i < len / 32; i += nt) bits[i] = 0;
+  if (pr.step > 0) {  // uniform
+    const uint64_t ge = __builtin_amdgcn_ballot_w64(pr.v >= t0);
+    if ((tid & 63) == 0) wfirst[tid >> 6] = ge ? (uint32_t)(tid + __builtin_ctzll(ge)) : 0xFFFFFFFFu;
   }
   __syncthreads();
+  // The first boundary at or after t0 is past probe f - 1 and at most probe
+  // f (f: the first thread whose probe is >= t0), i.e. in [f step, (f+1) step).
+  // No such probe: every offset is below t0 (the last probe reads the last).
+  int64_t lo = 0;
+  if (pr.step > 0) {
+    uint32_t f = 0xFFFFFFFFu;
+    for (int k = 0; k < nw; ++k) f = wfirst[k] < f ? wfirst[k] : f;
+    lo = f == 0xFFFFFFFFu ? seg.m : (int64_t)f * pr.step;
+  }
   const int64_t t1 = t0 + len;
-  for (int64_t j = *first + tid; j < seg.m; j += blockDim.x) {
-    const int64_t b = seg.off[j];  // >= t0: j is at or after the first such boundary
-    if (b >= t1) break;            // the offsets do not decrease: later ones are past the tile too
-    atomicOr(&bits[(b - t0) >> 5], 1u << ((b - t0) & 31));
+  for (int64_t j = lo + tid; j < seg.m; j += nt) {
+    const int64_t b = seg.off[j];
+    if (b >= t1) break;  // the offsets do not decrease: later ones are past the tile too
+    if (b >= t0) atomicOr(&bits[(b - t0) >> 5], 1u << ((b - t0) & 31));
   }
   __syncthreads();
   w.take_heads(bits, t0);
@@ -491,11 +505,14 @@ __global__ __launch_bounds__(1024) void scan_tile_sums_kernel(F f, const elem_t<
                                                               Acc* sums) {
   __shared__ Acc lds[kMaxWaves];
   __shared__ uint32_t heads_sh[IsSeg<Acc>::value ? kTileWords : 1];
-  __shared__ int64_t first_sh;
+  __shared__ uint32_t wfirst_sh[kMaxWaves];
   auto w = scan_wave_at<F, S, Acc>(blockIdx.x, n);
+  HeadProbe pr{0, 0};
+  if constexpr (IsSeg<Acc>::value) pr = heads_probe(seg);
   w.template load<kAligned>(x, seg);
   if constexpr (IsSeg<Acc>::value)
-    tile_heads(w, seg, (int64_t)blockIdx.x * blockDim.x * kScanE, (int64_t)blockDim.x * kScanE, heads_sh, &first_sh);
+    tile_heads(w, seg, pr, (int64_t)blockIdx.x * blockDim.x * kScanE, (int64_t)blockDim.x * kScanE, heads_sh,
+               wfirst_sh);
   w.fold(f);
   Acc total;
   (void)block_wave_prefix(w.wave_total, lds, &total);
@@ -551,12 +568,15 @@ __global__ __launch_bounds__(1024) void scan_tiles_kernel(F f, const elem_t<S>* 
                                                           int exclusive) {
   __shared__ Acc lds[kMaxWaves];
   __shared__ uint32_t heads_sh[IsSeg<Acc>::value ? kTileWords : 1];
-  __shared__ int64_t first_sh;
+  __shared__ uint32_t wfirst_sh[kMaxWaves];
   __shared__ u32x4 stage_sh[kStageVecs<S, Acc>];
   auto w = scan_wave_at<F, S, Acc>(blockIdx.x, n);
+  HeadProbe pr{0, 0};
+  if constexpr (IsSeg<Acc>::value) pr = heads_probe(seg);
   w.template load<kAligned>(x, seg);
   if constexpr (IsSeg<Acc>::value)
-    tile_heads(w, seg, (int64_t)blockIdx.x * blockDim.x * kScanE, (int64_t)blockDim.x * kScanE, heads_sh, &first_sh);
+    tile_heads(w, seg, pr, (int64_t)blockIdx.x * blockDim.x * kScanE, (int64_t)blockDim.x * kScanE, heads_sh,
+               wfirst_sh);
   w.fold(f);
   Acc total;
   const Acc before = block_wave_prefix(w.wave_total, lds, &total);
@@ -848,16 +868,20 @@ scan_onepass_kernel(F f, const elem_t<S>* x, int64_t n, SegSpec seg,
   __shared__ typename C::T carry_sh;
   __shared__ uint32_t slots[kTreeLevels * C::kWords * 64];
   __shared__ uint32_t heads_sh[IsSeg<Acc>::value ? kTileWords : 1];
-  __shared__ int64_t first_sh;
+  __shared__ uint32_t wfirst_sh[kMaxWaves];
   __shared__ u32x4 stage_sh[kStageVecs<S, Acc>];
   __shared__ uint32_t park_sh[IsSeg<Acc>::value ? ScanWave<F, S, Acc>::kStashWords * 64 : 1];
+  // The probes of the segment-start search do not depend on the tile: they
+  // go out with the ticket.
+  HeadProbe pr{0, 0};
+  if constexpr (IsSeg<Acc>::value) pr = heads_probe(seg);
   if (threadIdx.x == 0) tile_sh = (int64_t)atomicAdd(lb.ticket, 1u);
   __syncthreads();
   const int64_t tile = tile_sh;
   auto w = scan_wave_at<F, S, Acc>(tile, n);
   w.template load<kAligned>(x, seg);
   if constexpr (IsSeg<Acc>::value)
-    tile_heads(w, seg, tile * blockDim.x * kScanE, (int64_t)blockDim.x * kScanE, heads_sh, &first_sh);
+    tile_heads(w, seg, pr, tile * blockDim.x * kScanE, (int64_t)blockDim.x * kScanE, heads_sh, wfirst_sh);
   w.fold(f);
   Acc total;
   const Acc before = block_wave_prefix(w.wave_total, lds, &total);
