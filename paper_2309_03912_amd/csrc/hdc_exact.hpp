@@ -1,11 +1,12 @@
 // Exact sum of bfloat16 values: the real sum of the inputs, rounded once to
 // fp64, whatever the summation order, tuning or grid -- bit-reproducible.
 //
-// Every finite bf16 value is m * 2^(q - 133) with an integer m < 2^8 and a
-// position q in [0, 253] (q = E - 1 for a biased exponent E >= 1, q = 0 for
-// subnormals).  Writing q = 32 d + r, the value is (m << r) * 2^(32 d - 133):
-// an integer below 2^39 added to digit d (d in [0, 7]) of a fixed-point
-// number whose digit j has the unit 2^(32 j - 133).  Each thread keeps its
+// Every finite bf16 value is m * 2^(E - 134) with an integer m < 2^8 and its
+// biased exponent E in [0, 254] (m = 128 + the fraction for E >= 1; for
+// subnormals, E = 0, m is twice the fraction).  Writing E = 32 d + r, the
+// value is (m << r) * 2^(32 d - 134): an integer below 2^39 added to digit d
+// (d in [0, 7]) of a fixed-point number whose digit j has the unit
+// 2^(32 j - 134).  Each thread keeps its
 // eight digits as fp64 accumulators in LDS (integers below 2^53, so every
 // add is exact; no carries while folding) and adds each term to its digit
 // by address.  Lanes, wavefronts and blocks then add digit by digit as
@@ -25,7 +26,7 @@
 
 namespace hdc {
 
-constexpr int kExactDigits = 10;  // units 2^-133 .. 2^155: every sum of < 2^31 bf16 values
+constexpr int kExactDigits = 10;  // units 2^-134 .. 2^154: every sum of < 2^31 bf16 values
 constexpr int kExactFoldDigits = 8;  // digits that receive terms directly
 
 // Fold state: digits (carry-save) and the non-finite flags
@@ -79,14 +80,14 @@ struct Bf16Exact {
         g[j] = v;
       }
     }
-    int top = -1;  // highest set bit; bit 0 has the value 2^-133
+    int top = -1;  // highest set bit; bit 0 has the value 2^-134
     for (int j = kExactDigits - 1; j >= 0 && top < 0; --j)
       if (g[j]) top = 32 * j + 31 - __builtin_clz(g[j]);
     if (top < 0) return 0.0;
     auto bit = [&](int i) -> uint64_t { return (g[i >> 5] >> (i & 31)) & 1u; };
     double r;
     if (top < 53) {
-      r = __builtin_ldexp((double)((uint64_t)g[0] | ((uint64_t)g[1] << 32)), -133);  // exact
+      r = __builtin_ldexp((double)((uint64_t)g[0] | ((uint64_t)g[1] << 32)), -134);  // exact
     } else {
       const int sh = top - 52;  // keep bits [sh, top]
       uint64_t m = 0;
@@ -95,7 +96,7 @@ struct Bf16Exact {
       uint64_t sticky = 0;
       for (int i = sh - 2; i >= 0 && !sticky; --i) sticky = bit(i);
       if (guard && (sticky || (m & 1u))) m += 1;  // m <= 2^53: exact as a double
-      r = __builtin_ldexp((double)m, sh - 133);
+      r = __builtin_ldexp((double)m, sh - 134);
     }
     return neg ? -r : r;
   }
@@ -103,10 +104,10 @@ struct Bf16Exact {
 
 // Pass 1: every block folds its grid-stride share of 16-byte vectors (8
 // values; head and tail elements by the last block) into one state.  The
-// decode is branch-free: a value's term m 2^(q mod 32) (an integer below
+// decode is branch-free: a value's term m 2^(E mod 32) (an integer below
 // 2^39, signed) is formed as an fp64 number (the value widened and scaled
-// by 2^(133 - 32 d)), which holds it exactly, and added to the lane's fp64
-// accumulator of digit q / 32 -- exact while a lane
+// by 2^(134 - 32 d)), which holds it exactly, and added to the lane's fp64
+// accumulator of digit E / 32 -- exact while a lane
 // takes fewer than 2^14 terms, which the launch guarantees (at most 1024
 // vectors per lane, kExactVecsPerLane).  The accumulators live in LDS, digit
 // j of thread i at dig[j * blockDim + i], so a term goes to its own digit by
@@ -114,9 +115,9 @@ struct Bf16Exact {
 // the thread that owns a slot touches it.  Infinities and NaNs are added to
 // a ninth slot that is never read (a select of the address, not of the
 // fp64 term); their flags are taken on a separate, rare path.  A term costs
-// ten vector instructions and the LDS add; the slot address is one 24-bit
+// nine vector instructions and the LDS add; the slot address is one 24-bit
 // multiply-add (with a select of the term and a 64-bit address, thirteen:
-// 9% slower at 2^28).  (Building the fp64 term from the bf16 bits with
+// 10% slower at 2^28).  (Building the fp64 term from the bf16 bits with
 // integer operations instead of the widening and ldexp measured 20% slower.)
 constexpr int64_t kExactVecsPerLane = 1024;  // 8192 terms (+2 head/tail) < 2^14
 constexpr int kExactMaxBlock = 512;          // 9 slots x 8 bytes x 512 threads = 36 KiB of LDS
@@ -130,26 +131,26 @@ __global__ __launch_bounds__(kExactMaxBlock) void exact_bf16_kernel(const uint16
   const int64_t B = blockDim.x, tid = threadIdx.x;
 #pragma unroll
   for (int j = 0; j <= kExactFoldDigits; ++j) dig[j * B + tid] = 0.0;
-  // LDS byte address of this thread's slot of digit d: own + 8 B d = own +
-  // (32 d) (B / 4), one 24-bit multiply-add from q & 0xE0 = 32 d.  Slot
-  // kExactFoldDigits is the sink for infinities and NaNs (never read).
+  // LDS byte address of this thread's slot of digit d: own + 8 B d, one
+  // 24-bit multiply-add (d is bits 12-14 of the bf16 word, the top three bits
+  // of E).  Slot kExactFoldDigits is the sink for infinities and NaNs (never
+  // read); a class test of the widened value picks it.
   using lds_f64 = __attribute__((address_space(3))) double;
-  const uint32_t own = (uint32_t)(uintptr_t)(lds_f64*)(dig + tid), quarter = (uint32_t)B >> 2;
-  const uint32_t sink = own + 8u * (uint32_t)B * kExactFoldDigits;
+  const uint32_t own = (uint32_t)(uintptr_t)(lds_f64*)(dig + tid), stride = 8u * (uint32_t)B;
+  const uint32_t sink = own + stride * kExactFoldDigits;
   uint32_t nf = 0;
   auto fold = [&](const uint32_t (&u)[V]) {  // u: bf16 bits, 0 for no value
     bool special = false;
 #pragma unroll
     for (int i = 0; i < V; ++i) {
-      const uint32_t E = (u[i] >> 7) & 0xFFu;
-      special = special || E == 0xFFu;
-      const uint32_t q = (E > 1u ? E : 1u) - 1u;  // E - 1, or 0 for subnormals
-      const uint32_t d32 = q & 0xE0u;              // 32 d
+      const uint32_t d = (u[i] >> 12) & 7u;  // E / 32
       // the value itself (bf16 is the top half of binary32; subnormals are kept),
-      // scaled by 2^(133 - 32 d): the signed integer m 2^(q mod 32), exact in fp64
+      // scaled by 2^(134 - 32 d): the signed integer m 2^(E mod 32), exact in fp64
       const float v = __builtin_bit_cast(float, u[i] << 16);
-      const double t = __builtin_ldexp((double)v, 133 - (int)d32);
-      const uint32_t at = E == 0xFFu ? sink : own + d32 * quarter;
+      const bool fin = __builtin_isfinite(v);
+      special = special || !fin;
+      const double t = __builtin_ldexp((double)v, 134 - 32 * (int)d);
+      const uint32_t at = fin ? own + d * stride : sink;
       __hip_atomic_fetch_add((lds_f64*)(uintptr_t)at, t, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_WORKGROUP);
     }
