@@ -161,16 +161,23 @@ __global__ __launch_bounds__(kExactMaxBlock) void exact_bf16_kernel(const uint16
     }
   };
   const uint16_t* xv = x + r.head;
-  const int64_t nchunk = (r.nvec + B * U - 1) / (B * U);
+  const int64_t cv = B * U;  // vectors per chunk
+  const int64_t nchunk = (r.nvec + cv - 1) / cv;
+  // The chunk's loads go through a raw buffer resource based at the chunk
+  // and ending at its last vector (word 3 0x00020000: 32-bit data format, no
+  // swizzle; cache policy 2: non-temporal): lane offsets stay fixed, and a
+  // load past the end returns zeros, which add nothing.
+  uint32_t vo[U];
+#pragma unroll
+  for (int w = 0; w < U; ++w) vo[w] = (uint32_t)(tid + w * B) * 16u;
   for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
-    const int64_t base = c * B * U + tid;
+    const int64_t v0 = c * cv;
+    const int32_t bytes = (int32_t)((r.nvec - v0 < cv ? r.nvec - v0 : cv) * 16);
+    const __amdgpu_buffer_rsrc_t rx =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(xv + v0 * V), (short)0, bytes, 0x00020000);
     u32x4 a[U];
 #pragma unroll
-    for (int w = 0; w < U; ++w) {
-      const int64_t vi = base + w * B;
-      a[w] = vi < r.nvec ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(xv + vi * V))
-                         : u32x4{0u, 0u, 0u, 0u};
-    }
+    for (int w = 0; w < U; ++w) a[w] = __builtin_amdgcn_raw_buffer_load_b128(rx, vo[w], 0, 2);
 #pragma unroll
     for (int w = 0; w < U; ++w) {
       uint32_t u[V];
