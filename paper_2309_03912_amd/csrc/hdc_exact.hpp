@@ -296,16 +296,26 @@ __global__ __launch_bounds__(1024) void exact_f16_dot_kernel(const uint16_t* __r
     constexpr int V = 8;
     const uint16_t* xv = x + r.head;
     const uint16_t* zv = z + r.head;
-    const int64_t nchunk = (r.nvec + B * U - 1) / (B * U);
+    const int64_t cv = B * U;  // vectors per chunk
+    const int64_t nchunk = (r.nvec + cv - 1) / cv;
+    // Loads through raw buffer resources based at the chunk and ending at its
+    // last vector, as in exact_bf16_kernel: zeros past the end (a product of
+    // zeros adds nothing), fixed lane offsets.
+    uint32_t vo[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) vo[u] = (uint32_t)(tid + u * B) * 16u;
     for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
-      const int64_t base = c * B * U + tid;
+      const int64_t v0 = c * cv;
+      const int32_t bytes = (int32_t)((r.nvec - v0 < cv ? r.nvec - v0 : cv) * 16);
+      const __amdgpu_buffer_rsrc_t rx =
+          __builtin_amdgcn_make_buffer_rsrc((void*)(xv + v0 * V), (short)0, bytes, 0x00020000);
+      const __amdgpu_buffer_rsrc_t rz =
+          __builtin_amdgcn_make_buffer_rsrc((void*)(zv + v0 * V), (short)0, bytes, 0x00020000);
       u32x4 a[U], b[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int64_t vi = base + u * B;
-        const bool in = vi < r.nvec;
-        a[u] = in ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(xv + vi * V)) : u32x4{0u, 0u, 0u, 0u};
-        b[u] = in ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(zv + vi * V)) : u32x4{0u, 0u, 0u, 0u};
+        a[u] = __builtin_amdgcn_raw_buffer_load_b128(rx, vo[u], 0, 2);
+        b[u] = __builtin_amdgcn_raw_buffer_load_b128(rz, vo[u], 0, 2);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
