@@ -60,15 +60,30 @@ __global__ __launch_bounds__(1024) void batch_kernel(FM fm, F f, BatchTable t, A
     for (int k = 0; k < KV; ++k) acc[k] = Acc::zero();
     const elem_t<S>* xv = x + r.head;
     const int64_t vend = (lc + 1) * t.chunk_vecs < r.nvec ? (lc + 1) * t.chunk_vecs : r.nvec;
-    auto step = [&](int64_t base, auto full_c) {
+    // Int32 calls (a quarter-rate multiply per element) load and store
+    // through raw buffer resources based at the step and ending at the
+    // chunk's last vector (word 3 0x00020000: 32-bit data format, no swizzle;
+    // cache policy 2: non-temporal): fixed lane offsets instead of 64-bit
+    // address arithmetic per access; past the end, loads return zeros (the
+    // mask leaves them out) and stores are dropped.
+    constexpr bool kBuf = std::is_same_v<S, I32>;
+    auto step = [&](int64_t v0, auto full_c) {
       constexpr bool kFull = decltype(full_c)::value;
+      const int64_t base = v0 + tid;
+      const int32_t bytes = kBuf ? (int32_t)((vend - v0 < B * U ? vend - v0 : B * U) * 16) : 0;
       Vec<S> a[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        if (kFull || base + u * B < vend)
+        if constexpr (kBuf) {
+          const __amdgpu_buffer_rsrc_t rx =
+              __builtin_amdgcn_make_buffer_rsrc((void*)(xv + v0 * KV), (short)0, bytes, 0x00020000);
+          const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(rx, (uint32_t)(tid + u * B) * 16u, 0, 2);
+          __builtin_memcpy(&a[u], &w, 16);
+        } else if (kFull || base + u * B < vend) {
           a[u] = load16<S>(xv + (base + u * B) * KV);
-        else
+        } else {
           a[u] = Vec<S>{};
+        }
       }
       elem_t<S> v[N];
 #pragma unroll
@@ -94,7 +109,13 @@ __global__ __launch_bounds__(1024) void batch_kernel(FM fm, F f, BatchTable t, A
         map_batch<FM, S>(fm, v, o);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          if (kFull || base + u * B < vend) {
+          if constexpr (kBuf) {
+            const __amdgpu_buffer_rsrc_t ry =
+                __builtin_amdgcn_make_buffer_rsrc((void*)(y + r.head + v0 * KV), (short)0, bytes, 0x00020000);
+            u32x4 w;
+            __builtin_memcpy(&w, &o[u * KV], 16);
+            __builtin_amdgcn_raw_buffer_store_b128(w, ry, (uint32_t)(tid + u * B) * 16u, 0, 2);
+          } else if (kFull || base + u * B < vend) {
             Vec<S> ov;
 #pragma unroll
             for (int k = 0; k < KV; ++k) ov.e[k] = o[u * KV + k];
@@ -104,8 +125,8 @@ __global__ __launch_bounds__(1024) void batch_kernel(FM fm, F f, BatchTable t, A
       }
     };
     int64_t v0 = lc * t.chunk_vecs;
-    for (; v0 + B * U <= vend; v0 += B * U) step(v0 + tid, std::true_type{});
-    if (v0 < vend) step(v0 + tid, std::false_type{});
+    for (; v0 + B * U <= vend; v0 += B * U) step(v0, std::true_type{});
+    if (v0 < vend) step(v0, std::false_type{});
     if (lc == 0) {  // the first chunk also takes the unaligned head and tail
       if (tid < r.head) {
         fold_elem<F, S>(acc[0], f, x[tid], x[tid]);
