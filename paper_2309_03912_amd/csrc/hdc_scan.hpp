@@ -212,9 +212,17 @@ struct ScanWave {
   template <bool kAligned>
   __device__ void load(const elem_t<S>* x, const SegSpec& seg) {
     if (kAligned && wbase + 64 * kScanE <= n) {
+      // a raw buffer resource over this wavefront's part (word 3 0x00020000:
+      // 32-bit data format, no swizzle; cache policy 2: non-temporal), so the
+      // lane offsets stay fixed instead of 64-bit address arithmetic per load
+      const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(x + wbase), (short)0, (int)(64 * kScanE * sizeof(elem_t<S>)), 0x00020000);
       Vec<S> a[Q];
 #pragma unroll
-      for (int q = 0; q < Q; ++q) a[q] = load16<S>(x + index(q, 0));
+      for (int q = 0; q < Q; ++q) {
+        const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(rx, (uint32_t)(q * 64 + lane) * 16u, 0, 2);
+        __builtin_memcpy(&a[q], &w, 16);
+      }
 #pragma unroll
       for (int q = 0; q < Q; ++q)
 #pragma unroll
